@@ -1,0 +1,53 @@
+"""Pins of the oracle's MLP (16-64-64-1, ReLU, sigmoid, mean BCE) by central
+finite differences and of its Adam step by the update written out."""
+import numpy as np
+
+import oracle
+import synth
+
+
+def _params(seed=0):
+    r = synth.rng(seed)
+    n = oracle.mlp_nparams()
+    p = r.standard_normal(n) * 0.3
+    return p
+
+
+def test_gradient_central_differences():
+    P = _params(1)
+    X = synth.small_float(31, 40, 16)
+    y = (synth.rng(2).random(40) < 0.5).astype(np.float32)
+    loss, g, _ = oracle.mlp_fwd_bwd(P, X, y)
+    r = synth.rng(3)
+    idx = r.choice(P.shape[0], size=200, replace=False)
+    h = 1e-6
+    for i in idx:
+        a = P.copy(); a[i] += h
+        b = P.copy(); b[i] -= h
+        fd = (oracle.mlp_fwd_bwd(a, X, y, want_grad=False)[0] -
+              oracle.mlp_fwd_bwd(b, X, y, want_grad=False)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-8
+
+
+def test_forward_matches_numpy():
+    P = _params(4)
+    X = synth.small_float(32, 10, 16)
+    W1 = P[:1024].reshape(64, 16); b1 = P[1024:1088]
+    W2 = P[1088:5184].reshape(64, 64); b2 = P[5184:5248]
+    w3 = P[5248:5312]; b3 = P[5312]
+    h1 = np.maximum(X.astype(np.float64) @ W1.T + b1, 0)
+    h2 = np.maximum(h1 @ W2.T + b2, 0)
+    z = h2 @ w3 + b3
+    _, _, logits = oracle.mlp_fwd_bwd(P, X)
+    assert np.allclose(logits, z, rtol=1e-12, atol=1e-12)
+
+
+def test_adam_step():
+    P = _params(5)
+    g = _params(6)
+    m = np.zeros_like(P); v = np.zeros_like(P)
+    p1 = P.copy()
+    oracle.adam_step(p1, g, m, v, 1, lr=0.01)
+    # first step: m = (1-b1) g, v = (1-b2) g^2, bias corrected -> g / (|g| + eps')
+    expect = P - 0.01 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p1, expect, rtol=1e-9, atol=1e-12)
