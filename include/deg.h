@@ -1,0 +1,251 @@
+/*
+ * deg.h -- C ABI of the MI355X (gfx950) search library for the Dynamic
+ * Exploration Graph (DEG) of Hezel, Barthel, Schall and Jung (PVLDB 17).
+ *
+ * The library searches a DEG: an undirected, even-regular graph (every vertex
+ * has exactly `degree` neighbours, Sec. 5.1) over N base vectors, with the
+ * range search of Algorithm 1. It also computes exact kNN ground truth
+ * (Eq. knn) with matrix cores, builds reduced-precision vector stores, and
+ * trains and runs a small MLP that stops a search early.
+ *
+ * Conventions for every call:
+ *   - Pointers to arrays are DEVICE pointers owned by the caller unless the
+ *     comment says "host". The library never allocates device memory on the
+ *     search path; scratch memory is a caller-provided workspace sized by the
+ *     matching *_workspace_bytes call.
+ *   - Calls only enqueue work on `stream` (a hipStream_t; NULL = the null
+ *     stream) and return. Outputs are valid after the stream is synchronised.
+ *   - Host-side argument errors return a status at once and enqueue nothing.
+ *     Errors the device detects (an id outside [0, N)) set a bit in the
+ *     query's flags and its result row is padded.
+ *   - Distances: L2 is the SQUARED Euclidean distance; IP is 1 - <x, q>.
+ *   - Every ordering is by (distance, vertex id) ascending. Result rows are
+ *     padded with id -1 and distance +inf when fewer than k vertices are found.
+ *   - FP32 distances are reduced in one fixed order ("C32x4"): 32 partial
+ *     sums, chunk c of 4 consecutive dims goes to partial c mod 32 with fused
+ *     multiply-adds in increasing dim order, then a halving tree
+ *     p[i] += p[i + w] for w = 16, 8, 4, 2, 1.
+ */
+#ifndef DEG_H
+#define DEG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DEG_OK = 0,
+    DEG_ERR_INVALID_ARG = 1,
+    DEG_ERR_UNSUPPORTED = 2,
+    DEG_ERR_WORKSPACE = 3,
+    DEG_ERR_HIP = 4
+} deg_status;
+
+typedef enum { DEG_METRIC_L2 = 0, DEG_METRIC_IP = 1 } deg_metric;
+
+typedef enum { DEG_F32 = 0, DEG_BF16 = 1, DEG_FP8_E4M3 = 2 } deg_dtype;
+
+/* Per-query flag bits written to out_stats[q*4 + 2]. */
+#define DEG_FLAG_QUEUE_OVERFLOW 1 /* a live candidate was dropped because S was full */
+#define DEG_FLAG_HASH_SPILL 2     /* the visited set moved from LDS to the workspace */
+#define DEG_FLAG_HASH_FULL 4      /* the workspace visited table filled: search ended early */
+#define DEG_FLAG_BAD_ID 8         /* a seed, query vertex or adjacency id was outside [0, N) */
+#define DEG_FLAG_LEARNED_STOP 16  /* the stop predictor ended the search */
+
+/*
+ * Base vectors. `data` holds n rows of `row_stride` elements of `dtype`
+ * (row_stride >= dim). BF16 rows are the upper halves of FP32 values (round
+ * to nearest even). FP8 rows are OCP E4M3 codes with one FP32 scale per row
+ * (value = scale[i] * e4m3(code)). `f32_data` holds the FP32 rows
+ * (f32_stride elements each); it is read for the exact rerank and for the
+ * query vector of an exploratory search, and may equal `data` for DEG_F32.
+ */
+typedef struct {
+    const void *data;
+    int64_t n;
+    int32_t dim;
+    int32_t row_stride;
+    int32_t dtype;
+    int32_t metric;
+    const float *scale;
+    const float *f32_data;
+    int32_t f32_stride;
+    int32_t reserved;
+} deg_vectors;
+
+/*
+ * The graph: n rows of `row_stride` int32 neighbour ids, the first `degree`
+ * of which are the vertex's neighbours (Sec. 5.4: search reads ids only, no
+ * edge weights). degree must be even and >= 4 (Sec. 5.1) and <= 64.
+ */
+typedef struct {
+    const int32_t *adj;
+    int64_t n;
+    int32_t degree;
+    int32_t row_stride;
+} deg_graph;
+
+/*
+ * Learned early stop: a 16-64-64-1 MLP (ReLU, sigmoid) in BF16 as written by
+ * deg_mlp_export_bf16 (5313 values: W1[64][16], b1[64], W2[64][64], b2[64],
+ * w3[64], b3). Every `interval` hops the search computes its 16 state
+ * features; if sigmoid(logit) >= tau it stops. The plain rule of Algorithm 1
+ * still applies.
+ */
+typedef struct {
+    const uint16_t *weights_bf16; /* device */
+    const float *feat_mean;       /* device, 16: features are standardised */
+    const float *feat_inv_std;    /* device, 16 */
+    float tau;
+    int32_t interval;
+} deg_stop_model;
+
+/* Search options. Zero-initialised means: defaults. */
+typedef struct {
+    int32_t queue_cap;  /* capacity L of the candidate set S; 0 = default max(512, 8 k_pool) */
+    int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = default */
+    int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
+                           from f32_data when k_pool > k or dtype != DEG_F32; 0 = k */
+    int32_t rerank;     /* 1 = always rerank the pool in FP32, 0 = only when needed */
+    const deg_stop_model *stop; /* host pointer to the model descriptor, NULL = plain rule */
+    float *trace;       /* device; non-NULL = write stop-predictor training rows */
+    int64_t trace_rows_per_query; /* rows per query in `trace` (each 20 floats) */
+    int32_t trace_interval;       /* hops between two trace rows */
+    int32_t waves_per_block;      /* 0 = autotuned */
+} deg_search_opts;
+
+/*
+ * Workspace bytes needed by deg_search / deg_search_indexed / deg_search_batch
+ * for `nq` queries with results of size up to `k` and these options.
+ */
+size_t deg_search_workspace_bytes(const deg_vectors *v, const deg_graph *g, int64_t nq,
+                                  int32_t k, const deg_search_opts *o);
+
+/*
+ * RangeSearch (Algorithm 1) of nq query vectors, one wavefront per query.
+ *   queries   nq rows of q_stride FP32 (dim used)
+ *   seed_ids  nq x n_seeds distinct seed vertices (Sec. 5.4: the search starts
+ *             from the graph's median vertex, see deg_medoid)
+ *   k         results per query (1..512), eps >= 0 the range factor
+ *   out_ids   nq x k int32, out_dists nq x k FP32 (the traversal distance, or
+ *             the FP32 distance after a rerank)
+ *   out_stats nullable; nq x 4 int32 {hops, distance evaluations, flags, 0}
+ * With DEG_F32 data, no rerank and no stop model, the result equals the
+ * oracle's Algorithm 1 exactly: same ids, distances, hops and evaluations.
+ */
+deg_status deg_search(const deg_vectors *v, const deg_graph *g, const float *queries,
+                      int64_t nq, int64_t q_stride, const int32_t *seed_ids, int32_t n_seeds,
+                      int32_t k, float eps, const deg_search_opts *o, int32_t *out_ids,
+                      float *out_dists, int32_t *out_stats, void *workspace, size_t ws_bytes,
+                      void *stream);
+
+/*
+ * Exploratory search (Sec. 4 and 6.7): each query is a base vertex; the
+ * search starts at that vertex, uses its FP32 row as the query, and never
+ * returns it (other vertices at distance 0 are returned).
+ *   query_ids  nq vertex ids
+ */
+deg_status deg_search_indexed(const deg_vectors *v, const deg_graph *g, const int32_t *query_ids,
+                              int64_t nq, int32_t k, float eps, const deg_search_opts *o,
+                              int32_t *out_ids, float *out_dists, int32_t *out_stats,
+                              void *workspace, size_t ws_bytes, void *stream);
+
+/*
+ * A mixed stream of queries in one persistent launch fed by a device work
+ * queue. Each descriptor names its kind (0 = vector query, 1 = exploratory),
+ * its seed (kind 0) or vertex (kind 1), its query row (kind 0, a row of
+ * `queries`, which holds n_query_rows rows; may be NULL if every descriptor
+ * is exploratory), its own k (1..k_max) and eps, and where its k results
+ * start in out_ids / out_dists (the caller sizes those arrays). A descriptor
+ * outside these bounds is skipped and flagged DEG_FLAG_BAD_ID.
+ */
+typedef struct {
+    int32_t kind;
+    int32_t seed_or_vertex;
+    int64_t query_row;
+    int32_t k;
+    float eps;
+    int64_t out_offset;
+} deg_query_desc;
+
+deg_status deg_search_batch(const deg_vectors *v, const deg_graph *g, const float *queries,
+                            int64_t n_query_rows, int64_t q_stride, const deg_query_desc *descs,
+                            int64_t nq,
+                            int32_t k_max, const deg_search_opts *o, int32_t *out_ids,
+                            float *out_dists, int32_t *out_stats, void *workspace,
+                            size_t ws_bytes, void *stream);
+
+/*
+ * Exact k nearest neighbours (Eq. knn) by brute force on matrix cores.
+ * BF16 products with FP32 accumulation find candidates (exact for
+ * integer-valued data below 256); the best k + margin per query are then
+ * recomputed as direct FP32 differences in the C32x4 order and sorted by
+ * (distance, id). exclude_ids: nullable, one id per query kept out of its
+ * result (exploratory ground truth).
+ */
+size_t deg_knn_workspace_bytes(int64_t n, int32_t dim, int64_t nq, int32_t k);
+deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t dim, int64_t b_stride,
+                              const float *queries, int64_t nq, int64_t q_stride, int32_t k,
+                              int32_t metric, const int32_t *exclude_ids, int32_t *out_ids,
+                              float *out_dists, void *workspace, size_t ws_bytes, void *stream);
+
+/* The median (seed) vertex of Sec. 5.4: the vertex nearest to the coordinate
+ * mean (L2), or with the largest inner product with it (IP); ties -> smallest
+ * id. out_id: one int32 on the device. */
+size_t deg_medoid_workspace_bytes(int64_t n, int32_t dim);
+deg_status deg_medoid(const float *vec, int64_t n, int32_t dim, int64_t stride, int32_t metric,
+                      int32_t *out_id, void *workspace, size_t ws_bytes, void *stream);
+
+/* Reduced-precision stores. BF16: round to nearest even. FP8: per row
+ * scale = max|x| / 448 (1 if the row is zero), code = E4M3 round to nearest
+ * even of x / scale, saturating at 448. Rows beyond dim are zero-filled up to
+ * out_stride. */
+deg_status deg_encode_bf16(const float *x, int64_t n, int32_t dim, int64_t x_stride,
+                           uint16_t *out, int64_t out_stride, void *stream);
+deg_status deg_encode_fp8(const float *x, int64_t n, int32_t dim, int64_t x_stride,
+                          uint8_t *out, int64_t out_stride, float *scale, void *stream);
+
+/*
+ * Stop-predictor training (FP32): one fused forward + backward pass of the
+ * 16-64-64-1 MLP with mean binary cross-entropy over B rows, then one Adam
+ * step. params/m/v: 5313 FP32 each (layout as deg_stop_model). X: B x 16,
+ * y: B labels in {0,1}. grad (nullable, 5313) receives the gradient and
+ * loss (nullable, 1) the mean loss. step >= 1; lr = 0 skips the update.
+ */
+size_t deg_mlp_workspace_bytes(int64_t B);
+deg_status deg_mlp_train_step(float *params, float *m, float *v, const float *X, const float *y,
+                              int64_t B, int64_t step, float lr, float *grad, float *loss,
+                              void *workspace, size_t ws_bytes, void *stream);
+/* Logits of B rows with FP32 params (out: B floats). */
+deg_status deg_mlp_forward(const float *params, const float *X, int64_t B, float *out,
+                           void *stream);
+/* Logits of B rows with the BF16 weights the search uses (out: B floats). */
+deg_status deg_mlp_forward_bf16(const uint16_t *w, const float *X, int64_t B, float *out,
+                                void *stream);
+/* FP32 params -> BF16 weights for deg_stop_model. */
+deg_status deg_mlp_export_bf16(const float *params, uint16_t *out, void *stream);
+
+/*
+ * Autotuner table (written by the package's tuner, read at launch): for
+ * searches over `dtype` rows of `dim` dims on a graph of `degree`, with a pool
+ * size in the bucket kp_bucket (16, 64, 128, 256 or 512), use `hash_slots`
+ * LDS visited slots and at most `waves_per_cu` resident waves per CU
+ * (0 = as many as fit). Explicit deg_search_opts fields take precedence.
+ */
+deg_status deg_tune_register(int32_t dtype, int32_t dim, int32_t degree, int32_t kp_bucket,
+                             int32_t hash_slots, int32_t waves_per_cu);
+void deg_tune_clear(void);
+
+/* Number of compute units of the current device (for workspace sizing). */
+int32_t deg_device_cu_count(void);
+
+const char *deg_status_string(deg_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DEG_H */

@@ -1,0 +1,248 @@
+// Entry points deg_search, deg_search_indexed and deg_search_batch: argument
+// checks, launch configuration and the persistent launch.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include "deg.h"
+#include "host_util.h"
+#include "search_impl.h"
+
+namespace degk {
+
+__global__ void reset_counter_kernel(int32_t *c) { *c = 0; }
+
+static KernelFn pick_kernel(int dt, int metric, int qch, int rreg) {
+    switch (dt) {
+        case DT_F32: return pick_kernel_f32(metric, qch, rreg);
+        case DT_BF16: return pick_kernel_bf16(metric, qch, rreg);
+        default: return pick_kernel_fp8(metric, qch, rreg);
+    }
+}
+
+struct LaunchCfg {
+    KernelFn fn;
+    int H, hshift, L, scap, Hg, hgshift, rreg, qch;
+    size_t lds;
+    int grid;
+    size_t ws_bytes;
+};
+
+static int ilog2(int x) {
+    int s = 0;
+    while ((1 << s) < x) ++s;
+    return s;
+}
+
+static deg_status validate_common(const deg_vectors *v, const deg_graph *g, int32_t kmax,
+                                  const deg_search_opts *o, bool need_f32) {
+    if (!v || !g || !v->data || !g->adj) return DEG_ERR_INVALID_ARG;
+    if (v->n <= 0 || v->n != g->n || v->n > 0x7fffffffLL) return DEG_ERR_INVALID_ARG;
+    if (v->dim < 1 || v->row_stride < v->dim || (v->row_stride & 3)) return DEG_ERR_INVALID_ARG;
+    if (v->dtype < DEG_F32 || v->dtype > DEG_FP8_E4M3) return DEG_ERR_INVALID_ARG;
+    if (v->metric != DEG_METRIC_L2 && v->metric != DEG_METRIC_IP) return DEG_ERR_INVALID_ARG;
+    if (v->dtype == DEG_FP8_E4M3 && !v->scale) return DEG_ERR_INVALID_ARG;
+    if (((v->dim + 3) / 4 + 31) / 32 > 12) return DEG_ERR_UNSUPPORTED;
+    if (g->degree < 4 || (g->degree & 1) || g->degree > 64 || g->row_stride < g->degree)
+        return DEG_ERR_INVALID_ARG;
+    if (kmax < 1 || kmax > 512) return DEG_ERR_INVALID_ARG;
+    int kp = kmax;
+    if (o && o->k_pool > kp) kp = o->k_pool;
+    if (kp > 512) return DEG_ERR_INVALID_ARG;
+    bool rerank = v->dtype != DEG_F32 || (o && (o->rerank || o->k_pool > kmax));
+    if ((rerank || need_f32) && !v->f32_data) return DEG_ERR_INVALID_ARG;
+    if (v->f32_data && (v->f32_stride < v->dim || (v->f32_stride & 3))) return DEG_ERR_INVALID_ARG;
+    if (o && o->queue_cap < 0) return DEG_ERR_INVALID_ARG;
+    if (o && o->hash_slots && (o->hash_slots < 256 || o->hash_slots > 16384 ||
+                               (o->hash_slots & (o->hash_slots - 1))))
+        return DEG_ERR_INVALID_ARG;
+    if (o && o->stop) {
+        const deg_stop_model *s = o->stop;
+        if (!s->weights_bf16 || !s->feat_mean || !s->feat_inv_std || s->interval < 1)
+            return DEG_ERR_INVALID_ARG;
+    }
+    if (o && o->trace && (o->trace_rows_per_query < 1 || o->trace_interval < 1))
+        return DEG_ERR_INVALID_ARG;
+    return DEG_OK;
+}
+
+static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, int32_t kmax,
+                          const deg_search_opts *o) {
+    LaunchCfg c;
+    int kp = kmax;
+    if (o && o->k_pool > kp) kp = o->k_pool;
+    c.rreg = kp <= 64 ? 1 : (kp <= 128 ? 2 : (kp <= 256 ? 4 : 8));
+    int nch = (v->dim + 3) / 4;
+    int q = (nch + 31) / 32;
+    c.qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
+    int L = (o && o->queue_cap > 0) ? o->queue_cap : (8 * kp > 512 ? 8 * kp : 512);
+    c.L = L;
+    c.scap = L > kp ? L : kp;
+    const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);
+    int H = (o && o->hash_slots) ? o->hash_slots : (t ? t->hash_slots : (kp <= 32 ? 2048 : 4096));
+    c.H = H;
+    c.hshift = 32 - ilog2(H);
+    int Hg = 1 << 16;
+    while (Hg < 4 * H) Hg <<= 1;
+    c.Hg = Hg;
+    c.hgshift = 32 - ilog2(Hg);
+    c.lds = 4 * (size_t)H + 8 * (size_t)(c.scap + 64) + 8 * 64 * (size_t)c.rreg + 8 * 64 + 4 * 64 * 3;
+    c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg);
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(c.fn), 64,
+                                                     c.lds) != hipSuccess || nb < 1)
+        nb = 1;
+    int cus = deg_device_cu_count();
+    int64_t grid = (int64_t)nb * cus;
+    if (t && t->waves_per_cu > 0 && t->waves_per_cu < nb) grid = (int64_t)t->waves_per_cu * cus;
+    if (o && o->waves_per_block > 0) grid = (int64_t)o->waves_per_block * cus;
+    if (grid > nq) grid = nq;
+    if (grid < 1) grid = 1;
+    c.grid = (int)grid;
+    c.ws_bytes = 256 + (size_t)c.grid * (size_t)c.Hg * 4;
+    return c;
+}
+
+static deg_status launch(const LaunchCfg &c, SearchParams &P, void *ws, size_t ws_bytes,
+                         hipStream_t st) {
+    if (c.lds > 64 * 1024) return DEG_ERR_UNSUPPORTED;
+    if (ws_bytes < c.ws_bytes || !ws) return DEG_ERR_WORKSPACE;
+    P.counter = reinterpret_cast<int32_t *>(ws);
+    P.spill = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + 256);
+    P.L = c.L;
+    P.scap = c.scap;
+    P.H = c.H;
+    P.hshift = c.hshift;
+    P.Hg = c.Hg;
+    P.hgshift = c.hgshift;
+    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, P.counter);
+    hipLaunchKernelGGL(c.fn, dim3(c.grid), dim3(64), c.lds, st, P);
+    return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
+}
+
+static void fill_common(SearchParams &P, const deg_vectors *v, const deg_graph *g, int32_t k,
+                        const deg_search_opts *o) {
+    memset(&P, 0, sizeof(P));
+    P.vec = v->data;
+    P.scale = v->scale;
+    P.f32 = v->f32_data;
+    P.n = v->n;
+    P.dim = v->dim;
+    P.vstride = v->row_stride;
+    P.f32_stride = v->f32_stride;
+    P.adj = g->adj;
+    P.degree = g->degree;
+    P.astride = g->row_stride;
+    P.k = k;
+    P.kpool = (o && o->k_pool > k) ? o->k_pool : k;
+    P.rerank = (v->dtype != DEG_F32 || (o && (o->rerank || o->k_pool > k))) ? 1 : 0;
+    if (o && o->stop) {
+        P.stop_w = o->stop->weights_bf16;
+        P.stop_mean = o->stop->feat_mean;
+        P.stop_istd = o->stop->feat_inv_std;
+        float tau = o->stop->tau;
+        // sigmoid(z) >= tau  <=>  z >= log(tau / (1 - tau))
+        P.stop_tau = tau <= 0.f ? -__builtin_inff()
+                                : (tau >= 1.f ? __builtin_inff() : logf(tau / (1.f - tau)));
+        P.stop_interval = o->stop->interval;
+    }
+    if (o && o->trace) {
+        P.trace = o->trace;
+        P.trace_rows = o->trace_rows_per_query;
+        P.trace_interval = o->trace_interval;
+    }
+}
+
+}  // namespace degk
+
+using namespace degk;
+
+extern "C" size_t deg_search_workspace_bytes(const deg_vectors *v, const deg_graph *g, int64_t nq,
+                                             int32_t k, const deg_search_opts *o) {
+    if (validate_common(v, g, k, o, false) != DEG_OK || nq < 0) return 0;
+    return make_cfg(v, g, nq < 1 ? 1 : nq, k, o).ws_bytes;
+}
+
+extern "C" deg_status deg_search(const deg_vectors *v, const deg_graph *g, const float *queries,
+                                 int64_t nq, int64_t q_stride, const int32_t *seed_ids,
+                                 int32_t n_seeds, int32_t k, float eps, const deg_search_opts *o,
+                                 int32_t *out_ids, float *out_dists, int32_t *out_stats,
+                                 void *workspace, size_t ws_bytes, void *stream) {
+    deg_status s = validate_common(v, g, k, o, false);
+    if (s != DEG_OK) return s;
+    if (nq < 0 || (nq > 0 && (!queries || !seed_ids || !out_ids || !out_dists)))
+        return DEG_ERR_INVALID_ARG;
+    if (q_stride < v->dim || n_seeds < 1 || n_seeds > 64 || !(eps >= 0.f))
+        return DEG_ERR_INVALID_ARG;
+    if (nq == 0) return DEG_OK;
+    if (nq > 0x7fffffffLL) return DEG_ERR_INVALID_ARG;
+    LaunchCfg c = make_cfg(v, g, nq, k, o);
+    SearchParams P;
+    fill_common(P, v, g, k, o);
+    P.mode = MODE_VEC;
+    P.queries = queries;
+    P.qstride = q_stride;
+    P.seeds = seed_ids;
+    P.nseeds = n_seeds;
+    P.nq = nq;
+    P.eps = eps;
+    P.out_ids = out_ids;
+    P.out_dists = out_dists;
+    P.out_stats = out_stats;
+    return launch(c, P, workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" deg_status deg_search_indexed(const deg_vectors *v, const deg_graph *g,
+                                         const int32_t *query_ids, int64_t nq, int32_t k,
+                                         float eps, const deg_search_opts *o, int32_t *out_ids,
+                                         float *out_dists, int32_t *out_stats, void *workspace,
+                                         size_t ws_bytes, void *stream) {
+    deg_status s = validate_common(v, g, k, o, true);
+    if (s != DEG_OK) return s;
+    if (nq < 0 || (nq > 0 && (!query_ids || !out_ids || !out_dists))) return DEG_ERR_INVALID_ARG;
+    if (!(eps >= 0.f)) return DEG_ERR_INVALID_ARG;
+    if (nq == 0) return DEG_OK;
+    if (nq > 0x7fffffffLL) return DEG_ERR_INVALID_ARG;
+    LaunchCfg c = make_cfg(v, g, nq, k, o);
+    SearchParams P;
+    fill_common(P, v, g, k, o);
+    P.mode = MODE_INDEXED;
+    P.qids = query_ids;
+    P.nseeds = 1;
+    P.nq = nq;
+    P.eps = eps;
+    P.out_ids = out_ids;
+    P.out_dists = out_dists;
+    P.out_stats = out_stats;
+    return launch(c, P, workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+extern "C" deg_status deg_search_batch(const deg_vectors *v, const deg_graph *g,
+                                       const float *queries, int64_t n_query_rows, int64_t q_stride,
+                                       const deg_query_desc *descs, int64_t nq, int32_t k_max,
+                                       const deg_search_opts *o, int32_t *out_ids,
+                                       float *out_dists, int32_t *out_stats, void *workspace,
+                                       size_t ws_bytes, void *stream) {
+    deg_status s = validate_common(v, g, k_max, o, true);
+    if (s != DEG_OK) return s;
+    if (nq < 0 || (nq > 0 && (!descs || !out_ids || !out_dists))) return DEG_ERR_INVALID_ARG;
+    if (queries && (q_stride < v->dim || n_query_rows < 0)) return DEG_ERR_INVALID_ARG;
+    if (nq == 0) return DEG_OK;
+    if (nq > 0x7fffffffLL) return DEG_ERR_INVALID_ARG;
+    LaunchCfg c = make_cfg(v, g, nq, k_max, o);
+    SearchParams P;
+    fill_common(P, v, g, k_max, o);
+    P.kpool = (o && o->k_pool > 0) ? o->k_pool : 0;
+    P.mode = MODE_BATCH;
+    P.queries = queries;
+    P.nqrows = queries ? n_query_rows : 0;
+    P.qstride = q_stride;
+    P.descs = descs;
+    P.nseeds = 1;
+    P.nq = nq;
+    P.out_ids = out_ids;
+    P.out_dists = out_dists;
+    P.out_stats = out_stats;
+    return launch(c, P, workspace, ws_bytes, static_cast<hipStream_t>(stream));
+}

@@ -1,0 +1,6 @@
+// Search kernels over BF16 rows.
+#include "search_impl.h"
+
+namespace degk {
+KernelFn pick_kernel_bf16(int metric, int qch, int rreg) { return pick_m<DT_BF16>(metric, qch, rreg); }
+}  // namespace degk

@@ -1,0 +1,6 @@
+// Search kernels over FP32 rows.
+#include "search_impl.h"
+
+namespace degk {
+KernelFn pick_kernel_f32(int metric, int qch, int rreg) { return pick_m<DT_F32>(metric, qch, rreg); }
+}  // namespace degk

@@ -1,0 +1,498 @@
+// Kernel template of the DEG range search (Algorithm 1); instantiated per
+// storage type in search_f32.hip, search_bf16.hip and search_fp8.hip.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "deg.h"
+#include "search_kernel.h"
+#include "mlp_device.h"
+
+namespace degk {
+
+// ---------------------------------------------------------------- S (candidates)
+// Keeps only keys whose distance is <= thr (the live entries), in order.
+__device__ __forceinline__ int s_prune(uint64_t *Sq, int scnt, float thr) {
+    const int lane = lane_id();
+    const uint32_t othr = ord_of(thr);
+    int out = 0;
+    for (int base = 0; base < scnt; base += WAVE) {
+        int i = base + lane;
+        uint64_t kk = i < scnt ? Sq[i] : KEY_MAX;
+        bool live = i < scnt && (uint32_t)(kk >> 32) <= othr;
+        uint64_t lm = ballot(live);
+        wave_sync();
+        if (live) Sq[out + prefix_in(lm)] = kk;
+        out += __popcll(lm);
+        wave_sync();
+    }
+    return out;
+}
+
+// Removes the largest key (the (distance, id) maximum).
+__device__ __forceinline__ void s_evict_max(uint64_t *Sq, int &scnt) {
+    const int lane = lane_id();
+    uint64_t mx = 0;
+    int mi = -1;
+    for (int i = lane; i < scnt; i += WAVE) {
+        uint64_t kk = Sq[i];
+        if (mi < 0 || kk > mx) { mx = kk; mi = i; }
+    }
+    uint64_t g = wave_max_u64(mi < 0 ? 0 : mx);
+    uint64_t last = Sq[scnt - 1];
+    wave_sync();
+    if (mi >= 0 && mx == g) Sq[mi] = last;
+    scnt -= 1;
+    wave_sync();
+}
+
+// ---------------------------------------------------------------- R (results)
+template <int RREG>
+__device__ __forceinline__ uint64_t r_at(const uint64_t (&R)[RREG], int i) {
+    uint64_t v = KEY_MAX;
+#pragma unroll
+    for (int r = 0; r < RREG; ++r)
+        if (r == (i >> 6)) v = R[r];
+    return read_lane_u64(v, i & 63);
+}
+
+// Merges the offered candidate keys into the sorted result list (top-kp by
+// key). `total` counts every key ever offered; once it exceeds kp the radius
+// r is the kp-th distance (Algorithm 1: r changes when R overflows).
+// Returns true if an accepted key landed in the first `t10` positions.
+template <int RREG>
+__device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &total, bool &ovf,
+                                        int kp, uint64_t ck, bool offer, uint64_t *kst,
+                                        uint64_t *mbuf, int t10, int &naccepted) {
+    const int lane = lane_id();
+    uint64_t rlast = ovf ? r_at<RREG>(R, kp - 1) : KEY_MAX;
+    uint64_t om = ballot(offer);
+    bool acc = offer && ck < rlast;
+    uint64_t am = ballot(acc);
+    int na = __popcll(am);
+    if (!ovf) {
+        total += __popcll(om);
+        if (total > kp) ovf = true;
+    }
+    naccepted = na;
+    if (na == 0) return false;
+    if (acc) kst[prefix_in(am)] = ck;
+    wave_sync();
+    uint64_t ak = lane < na ? kst[lane] : KEY_MAX;
+    int rank_new = 0, myposR = 0;
+    int cntR[RREG];
+#pragma unroll
+    for (int r = 0; r < RREG; ++r) cntR[r] = 0;
+    for (int t = 0; t < na; ++t) {
+        uint64_t kt = kst[t];
+        rank_new += (kt < ak) ? 1 : 0;
+        int posR = 0;
+#pragma unroll
+        for (int r = 0; r < RREG; ++r) {
+            cntR[r] += (kt < R[r]) ? 1 : 0;
+            posR += __popcll(ballot(R[r] < kt));
+        }
+        if (lane == t) myposR = posR;
+    }
+#pragma unroll
+    for (int r = 0; r < RREG; ++r) {
+        int i = r * WAVE + lane;
+        if (i < rcnt) {
+            int pos = i + cntR[r];
+            if (pos < kp) mbuf[pos] = R[r];
+        }
+    }
+    int newpos = myposR + rank_new;
+    if (lane < na && newpos < kp) mbuf[newpos] = ak;
+    bool top = ballot(lane < na && newpos < t10) != 0;
+    rcnt = min(kp, rcnt + na);
+    wave_sync();
+#pragma unroll
+    for (int r = 0; r < RREG; ++r) {
+        int i = r * WAVE + lane;
+        R[r] = i < rcnt ? mbuf[i] : KEY_MAX;
+    }
+    wave_sync();
+    return top;
+}
+
+// ---------------------------------------------------------------- the kernel
+template <int DT, int METRIC, int QCH, int RREG>
+__global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = lane_id();
+    const int p = lane & 31;
+    int32_t *htab = reinterpret_cast<int32_t *>(smem);
+    uint64_t *Sq = reinterpret_cast<uint64_t *>(smem + 4 * (size_t)P.H);
+    uint64_t *mbuf = Sq + (P.scap + WAVE);
+    uint64_t *kst = mbuf + RREG * WAVE;
+    int32_t *cid = reinterpret_cast<int32_t *>(kst + WAVE);
+    float *cdist = reinterpret_cast<float *>(cid + WAVE);
+    float *hbuf = cdist + WAVE;
+
+    Visited V;
+    V.htab = htab;
+    V.gtab = P.spill + (size_t)blockIdx.x * (size_t)P.Hg;
+    V.H = P.H;
+    V.hshift = P.hshift;
+    V.Hg = P.Hg;
+    V.hgshift = P.hgshift;
+
+    const int nch = (P.dim + 3) >> 2;
+    const bool mask_tail = (P.dim & 3) != 0;
+    const int deg = P.degree;
+    const int hlimit = (3 * P.H) / 4;
+    const int glimit = (3 * P.Hg) / 4;
+
+    for (;;) {
+        int qi = 0;
+        if (lane == 0) qi = atomicAdd(P.counter, 1);
+        qi = uni(qi);
+        if ((int64_t)qi >= P.nq) break;
+
+        // ---- query descriptor
+        int kind = P.mode == MODE_INDEXED ? 1 : 0;
+        int k = P.k;
+        float eps = P.eps;
+        int64_t out_off = (int64_t)qi * P.k;
+        int64_t qrow = qi;
+        int32_t vtx = -1;
+        int ns = P.nseeds;
+        int32_t seed_l = -1;
+        if (P.mode == MODE_VEC) {
+            seed_l = lane < ns ? P.seeds[(int64_t)qi * ns + lane] : -1;
+        } else if (P.mode == MODE_INDEXED) {
+            vtx = P.qids[qi];
+            ns = 1;
+            seed_l = lane == 0 ? vtx : -1;
+        } else {
+            const deg_query_desc *D = P.descs + qi;
+            kind = D->kind;
+            k = D->k;
+            eps = D->eps;
+            out_off = D->out_offset;
+            qrow = D->query_row;
+            ns = 1;
+            if (kind == 1) vtx = D->seed_or_vertex;
+            seed_l = lane == 0 ? D->seed_or_vertex : -1;
+            // a descriptor outside what the launch was sized for is skipped
+            if (k < 1 || k > P.k || (kind != 0 && kind != 1) || !(eps >= 0.f) ||
+                (kind == 0 && (P.queries == nullptr || qrow < 0 || qrow >= P.nqrows))) {
+                if (P.out_stats != nullptr && lane == 0) {
+                    int32_t *st = P.out_stats + (int64_t)qi * 4;
+                    st[0] = 0;
+                    st[1] = 0;
+                    st[2] = DEG_FLAG_BAD_ID;
+                    st[3] = 0;
+                }
+                continue;
+            }
+        }
+        int kp = k;
+        if (P.kpool > kp) kp = P.kpool;
+        if (kp > RREG * WAVE) kp = RREG * WAVE;
+        const bool do_rerank = P.rerank && P.f32 != nullptr;
+        const float onep = __fadd_rn(1.0f, eps);
+        int flags = 0;
+        bool bad_query = kind == 1 && (vtx < 0 || (int64_t)vtx >= P.n);
+        if (bad_query) flags |= DEG_FLAG_BAD_ID;
+
+        // ---- query vector in registers (zero beyond dim)
+        const float *qp = kind == 1 ? (bad_query ? nullptr : P.f32 + (int64_t)vtx * P.f32_stride)
+                                    : P.queries + qrow * P.qstride;
+        float4 qv[QCH];
+#pragma unroll
+        for (int c = 0; c < QCH; ++c) {
+            int b = 4 * (p + 32 * c);
+            float e0 = 0.f, e1 = 0.f, e2 = 0.f, e3 = 0.f;
+            if (qp) {
+                if (b + 0 < P.dim) e0 = qp[b + 0];
+                if (b + 1 < P.dim) e1 = qp[b + 1];
+                if (b + 2 < P.dim) e2 = qp[b + 2];
+                if (b + 3 < P.dim) e3 = qp[b + 3];
+            }
+            qv[c] = make_float4(e0, e1, e2, e3);
+        }
+
+        // ---- reset state
+        for (int i = lane; i < P.H; i += WAVE) htab[i] = -1;
+        V.count = 0;
+        V.spilled = false;
+        wave_sync();
+        uint64_t R[RREG];
+#pragma unroll
+        for (int r = 0; r < RREG; ++r) R[r] = KEY_MAX;
+        int rcnt = 0, total = 0;
+        bool ovf = false;
+        float r = __builtin_inff();
+        int scnt = 0, hops = 0, evals = 0;
+        const int t10 = kp < 10 ? kp : 10;
+        int last_chg = 0, last_d1 = 0;
+        float dseed = __builtin_inff(), rprev = __builtin_inff();
+        float f_acc_s = 0.f, f_acc_r = 0.f;
+        int nrow = 0;
+
+        // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
+        if (!bad_query) {
+            bool sv = lane < ns && seed_l >= 0 && (int64_t)seed_l < P.n;
+            if (ballot(lane < ns && !sv) != 0) flags |= DEG_FLAG_BAD_ID;
+            bool isnew = visit_insert(V, seed_l, sv);
+            uint64_t nm = ballot(isnew);
+            int cnt = __popcll(nm);
+            V.count += cnt;
+            evals += cnt;
+            if (isnew) cid[prefix_in(nm)] = seed_l;
+            wave_sync();
+            int32_t cand = lane < cnt ? cid[lane] : -1;
+            float cd = batch_dist<DT, METRIC, QCH>(P, qv, cid, cdist, cnt, nch, mask_tail);
+            uint64_t ck = lane < cnt ? make_key(cd, cand) : KEY_MAX;
+            if (cnt > 0) dseed = key_dist(wave_min_u64(ck));
+            int na;
+            bool offer = lane < cnt && cand != vtx;
+            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, offer, kst, mbuf, t10, na);
+            r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
+            bool push = lane < cnt;
+            uint64_t pm = ballot(push);
+            if (push) Sq[scnt + prefix_in(pm)] = ck;
+            scnt += __popcll(pm);
+            wave_sync();
+            while (scnt > P.L) {
+                s_evict_max(Sq, scnt);
+                flags |= DEG_FLAG_QUEUE_OVERFLOW;
+            }
+        }
+
+        // ---- hop loop (Algorithm 1)
+        while (scnt > 0) {
+            // s <- argmin of S; S <- S \ {s}
+            uint64_t mn = KEY_MAX;
+            int mi = -1;
+            for (int i = lane; i < scnt; i += WAVE) {
+                uint64_t kk = Sq[i];
+                if (kk < mn) { mn = kk; mi = i; }
+            }
+            uint64_t gmin = wave_min_u64(mn);
+            uint64_t last = Sq[scnt - 1];
+            wave_sync();
+            if (mi >= 0 && mn == gmin) Sq[mi] = last;
+            scnt -= 1;
+            wave_sync();
+            const float ds = key_dist(gmin);
+            const float thr0 = thr_of(r, onep);
+            if (ds > thr0) break;  // too far away: return R
+            hops += 1;
+
+            // learned stop / trace rows every `interval` hops
+            const bool want_stop = P.stop_w != nullptr && (hops % P.stop_interval) == 0;
+            const bool want_trace = P.trace != nullptr && (hops % P.trace_interval) == 0 &&
+                                    nrow < P.trace_rows;
+            if (want_stop || want_trace) {
+                float f[NFEAT];
+                const int kq = min(k, rcnt);
+                const float d1 = rcnt > 0 ? key_dist(r_at<RREG>(R, 0)) : 0.f;
+                const float dk = kq > 0 ? key_dist(r_at<RREG>(R, kq - 1)) : 0.f;
+                f[0] = logf(1.0f + (float)hops);
+                f[1] = logf(1.0f + (float)evals);
+                f[2] = (kq > 0 && dk > 0.f) ? d1 / dk : 1.0f;
+                f[3] = (rcnt > 0 && dseed > 0.f && !__builtin_isinf(dseed)) ? d1 / dseed : 1.0f;
+                f[4] = (!__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f) ? r / rprev : 1.0f;
+                f[5] = logf(1.0f + (float)(hops - last_chg));
+                f[6] = logf(1.0f + (float)(hops - last_d1));
+                f[7] = f_acc_s;
+                f[8] = f_acc_r;
+                f[9] = (float)scnt / (float)P.L;
+                f[10] = __builtin_isinf(thr0) ? 0.f : fminf(ds / fmaxf(thr0, 1e-30f), 4.0f);
+                f[11] = eps;
+                f[12] = logf((float)k);
+                f[13] = (float)kind;
+                f[14] = logf(1.0f + (float)V.count);
+                f[15] = 1.0f;
+                rprev = r;
+                if (want_trace) {
+                    float *row = P.trace + ((int64_t)qi * P.trace_rows + nrow) * TRACE_W;
+                    if (lane < NFEAT) {
+                        float fv = 0.f;
+#pragma unroll
+                        for (int i = 0; i < NFEAT; ++i)
+                            if (i == lane) fv = f[i];
+                        row[lane] = fv;
+                    }
+                    if (lane == 17) row[17] = (float)qi;
+                    if (lane == 18) row[18] = (float)hops;
+                    if (lane == 19) row[19] = 0.f;
+                    nrow += 1;
+                }
+                if (want_stop) {
+                    float fs[NFEAT];
+#pragma unroll
+                    for (int i = 0; i < NFEAT; ++i)
+                        fs[i] = __fmul_rn(__fsub_rn(f[i], P.stop_mean[i]), P.stop_istd[i]);
+                    float z = mlp_logit_bf16(P.stop_w, fs, hbuf);
+                    if (z >= P.stop_tau) {
+                        flags |= DEG_FLAG_LEARNED_STOP;
+                        break;
+                    }
+                }
+            }
+
+            // N <- N(G,s) \ C ; C <- C u N
+            const int32_t s = key_id(gmin);
+            int32_t nb = -1;
+            bool bad = false;
+            if (lane < deg) {
+                nb = P.adj[(int64_t)s * P.astride + lane];
+                if (nb < 0 || (int64_t)nb >= P.n) { bad = true; nb = -1; }
+            }
+            if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
+            if (!V.spilled && V.count + deg > hlimit) {
+                visit_spill(V);
+                flags |= DEG_FLAG_HASH_SPILL;
+            }
+            if (V.spilled && V.count + deg > glimit) {
+                flags |= DEG_FLAG_HASH_FULL;
+                break;
+            }
+            bool isnew = visit_insert(V, nb, nb >= 0);
+            uint64_t nm = ballot(isnew);
+            int cnt = __popcll(nm);
+            V.count += cnt;
+            evals += cnt;
+            f_acc_s = 0.f;
+            f_acc_r = 0.f;
+            if (cnt == 0) continue;
+            if (isnew) cid[prefix_in(nm)] = nb;
+            wave_sync();
+            const int32_t cand = lane < cnt ? cid[lane] : -1;
+            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, cid, cdist, cnt, nch, mask_tail);
+            const uint64_t ck = lane < cnt ? make_key(cd, cand) : KEY_MAX;
+
+            // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
+            const uint64_t old_first = R[0];
+            int na;
+            bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, lane < cnt && cand != vtx, kst,
+                                     mbuf, t10, na);
+            if (chg) last_chg = hops;
+            if (read_lane_u64(R[0], 0) != read_lane_u64(old_first, 0)) last_d1 = hops;
+            r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
+
+            // S <- S u {n : delta(n,q) <= r (1 + eps)}
+            const float thr = thr_of(r, onep);
+            const bool push = lane < cnt && cd <= thr;
+            const uint64_t pm = ballot(push);
+            const int np = __popcll(pm);
+            f_acc_s = (float)np / (float)deg;
+            f_acc_r = (float)na / (float)deg;
+            if (np > 0) {
+                if (scnt + np > P.L) scnt = s_prune(Sq, scnt, thr);
+                if (push) Sq[scnt + prefix_in(pm)] = ck;
+                scnt += np;
+                wave_sync();
+                while (scnt > P.L) {
+                    s_evict_max(Sq, scnt);
+                    flags |= DEG_FLAG_QUEUE_OVERFLOW;
+                }
+            }
+        }
+
+        // ---- trace labels: 1 where the top-10 no longer changes afterwards
+        if (P.trace != nullptr) {
+            for (int i = lane; i < P.trace_rows; i += WAVE) {
+                float *row = P.trace + ((int64_t)qi * P.trace_rows + i) * TRACE_W;
+                float lab = -1.0f;
+                if (i < nrow) lab = (P.trace_interval * (i + 1) > last_chg) ? 1.0f : 0.0f;
+                row[16] = lab;
+            }
+        }
+
+        // ---- exact FP32 rerank of the pool
+        if (do_rerank && rcnt > 0) {
+            uint64_t NK[RREG];
+#pragma unroll
+            for (int r2 = 0; r2 < RREG; ++r2) {
+                int base = r2 * WAVE;
+                int cntr = rcnt - base;
+                cntr = cntr < 0 ? 0 : (cntr > WAVE ? WAVE : cntr);
+                NK[r2] = KEY_MAX;
+                if (cntr > 0) {
+                    int32_t id = lane < cntr ? key_id(R[r2]) : 0;
+                    cid[lane] = id;
+                    wave_sync();
+                    float dd = batch_dist<DT, METRIC, QCH, true>(P, qv, cid, cdist, cntr, nch, mask_tail);
+                    NK[r2] = lane < cntr ? make_key(dd, id) : KEY_MAX;
+                    wave_sync();
+                }
+            }
+#pragma unroll
+            for (int r2 = 0; r2 < RREG; ++r2) mbuf[r2 * WAVE + lane] = NK[r2];
+            wave_sync();
+            int rank[RREG];
+#pragma unroll
+            for (int r2 = 0; r2 < RREG; ++r2) rank[r2] = 0;
+            for (int t = 0; t < rcnt; ++t) {
+                uint64_t kt = mbuf[t];
+#pragma unroll
+                for (int r2 = 0; r2 < RREG; ++r2) rank[r2] += (kt < NK[r2]) ? 1 : 0;
+            }
+#pragma unroll
+            for (int r2 = 0; r2 < RREG; ++r2)
+                if (r2 * WAVE + lane < rcnt) Sq[rank[r2]] = NK[r2];
+            wave_sync();
+#pragma unroll
+            for (int r2 = 0; r2 < RREG; ++r2) {
+                int i = r2 * WAVE + lane;
+                R[r2] = i < rcnt ? Sq[i] : KEY_MAX;
+            }
+            wave_sync();
+        }
+
+        // ---- output: R sorted by (distance, id), padded with (-1, +inf)
+#pragma unroll
+        for (int r2 = 0; r2 < RREG; ++r2) {
+            int i = r2 * WAVE + lane;
+            if (i < k) {
+                bool have = i < rcnt;
+                P.out_ids[out_off + i] = have ? key_id(R[r2]) : -1;
+                P.out_dists[out_off + i] = have ? key_dist(R[r2]) : __builtin_inff();
+            }
+        }
+        if (P.out_stats != nullptr && lane == 0) {
+            int32_t *st = P.out_stats + (int64_t)qi * 4;
+            st[0] = hops;
+            st[1] = evals;
+            st[2] = flags;
+            st[3] = 0;
+        }
+    }
+}
+
+using KernelFn = void (*)(SearchParams);
+
+template <int DT, int METRIC, int QCH>
+static KernelFn pick_r(int rreg) {
+    switch (rreg) {
+        case 1: return search_kernel<DT, METRIC, QCH, 1>;
+        case 2: return search_kernel<DT, METRIC, QCH, 2>;
+        case 4: return search_kernel<DT, METRIC, QCH, 4>;
+        default: return search_kernel<DT, METRIC, QCH, 8>;
+    }
+}
+template <int DT, int METRIC>
+static KernelFn pick_q(int qch, int rreg) {
+    switch (qch) {
+        case 1: return pick_r<DT, METRIC, 1>(rreg);
+        case 2: return pick_r<DT, METRIC, 2>(rreg);
+        case 4: return pick_r<DT, METRIC, 4>(rreg);
+        default: return pick_r<DT, METRIC, 12>(rreg);
+    }
+}
+template <int DT>
+static KernelFn pick_m(int metric, int qch, int rreg) {
+    return metric == DEG_METRIC_L2 ? pick_q<DT, DEG_METRIC_L2>(qch, rreg)
+                                   : pick_q<DT, DEG_METRIC_IP>(qch, rreg);
+}
+
+KernelFn pick_kernel_f32(int metric, int qch, int rreg);
+KernelFn pick_kernel_bf16(int metric, int qch, int rreg);
+KernelFn pick_kernel_fp8(int metric, int qch, int rreg);
+
+}  // namespace degk

@@ -1,0 +1,344 @@
+// Device code of the DEG range search (Algorithm 1) for gfx950.
+//
+// One wavefront (64 lanes) runs one query at a time; a persistent grid pulls
+// queries from a device counter. Per-wave state:
+//   visited set C   open-addressing int32 hash in LDS (spills to a per-wave
+//                   table in the workspace when 3/4 full), exact
+//   candidates S    unsorted (key) array in LDS with capacity L; keys are
+//                   (orderable distance bits << 32 | id), so one 64-bit
+//                   compare is the (distance, id) order
+//   results R       sorted keys in registers, RREG per lane (up to 64*RREG)
+// Each hop expands one row: the adjacency row is read by `degree` lanes, the
+// unchecked ids are compacted with a ballot, and each half-wave computes one
+// distance at a time with 32 partial sums (lane p of the half owns chunks
+// p, p+32, ...), reduced by an xor butterfly that pairs the same partials as
+// the halving tree, so every lane ends with the exact fixed-order sum.
+//
+// A row is merged as one batch. This gives the same ids, hops and
+// evaluations as the sequential loop of Algorithm 1: R after a row is the
+// top-k of R plus the row's candidates; a candidate the batch keeps out of S
+// (distance above the end-of-row threshold) could never be expanded, because
+// the radius only shrinks; and entries above the threshold are dropped from S
+// before any live entry is evicted for capacity.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "deg.h"
+
+namespace degk {
+
+constexpr int WAVE = 64;
+constexpr uint64_t KEY_MAX = ~0ull;
+
+enum { DT_F32 = 0, DT_BF16 = 1, DT_FP8 = 2 };
+enum { MODE_VEC = 0, MODE_INDEXED = 1, MODE_BATCH = 2 };
+
+// Trace row layout (floats): 16 features, label, query index, hop, reserved.
+constexpr int TRACE_W = 20;
+constexpr int NFEAT = 16;
+
+struct SearchParams {
+    // vectors
+    const void *vec;
+    const float *scale;
+    const float *f32;
+    int64_t n;
+    int32_t dim;
+    int32_t vstride;
+    int32_t f32_stride;
+    // graph
+    const int32_t *adj;
+    int32_t degree;
+    int32_t astride;
+    // queries
+    int32_t mode;
+    const float *queries;
+    int64_t qstride;
+    const int32_t *seeds;
+    int32_t nseeds;
+    const int32_t *qids;
+    const deg_query_desc *descs;
+    int64_t nq;
+    int32_t k;
+    int32_t kpool;  // traversal pool (>= k); batch: used when > descriptor k
+    float eps;
+    int32_t rerank;
+    // state sizes
+    int32_t L;      // capacity of S
+    int32_t scap;   // LDS slots of the S array beyond the 64 staging ones (>= L and >= pool)
+    int64_t nqrows; // rows of `queries` (batch mode bound check)
+    int32_t H;      // LDS hash slots (power of 2)
+    int32_t hshift; // 32 - log2(H)
+    int32_t Hg;     // workspace hash slots per wave (power of 2)
+    int32_t hgshift;
+    // outputs
+    int32_t *out_ids;
+    float *out_dists;
+    int32_t *out_stats;
+    // workspace
+    int32_t *counter;
+    int32_t *spill;
+    // learned stop
+    const uint16_t *stop_w;
+    const float *stop_mean;
+    const float *stop_istd;
+    float stop_tau;
+    int32_t stop_interval;
+    // trace
+    float *trace;
+    int64_t trace_rows;
+    int32_t trace_interval;
+};
+
+// ---------------------------------------------------------------- keys
+__device__ __forceinline__ uint32_t ord_of(float f) {
+    uint32_t u = __float_as_uint(f);
+    if (u == 0x80000000u) u = 0u;  // -0 orders as +0
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float f_of_ord(uint32_t o) {
+    uint32_t u = (o & 0x80000000u) ? (o & 0x7fffffffu) : ~o;
+    return __uint_as_float(u);
+}
+__device__ __forceinline__ uint64_t make_key(float d, int32_t id) {
+    return ((uint64_t)ord_of(d) << 32) | (uint32_t)id;
+}
+__device__ __forceinline__ float key_dist(uint64_t k) { return f_of_ord((uint32_t)(k >> 32)); }
+__device__ __forceinline__ int32_t key_id(uint64_t k) { return (int32_t)(uint32_t)k; }
+
+// ---------------------------------------------------------------- wave helpers
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ int lane_id() { return (int)threadIdx.x & (WAVE - 1); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ int prefix_in(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, int l) {
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, l);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), l);
+    return ((uint64_t)hi << 32) | lo;
+}
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    uint32_t lo = __shfl_xor((int)(uint32_t)v, m);
+    uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | (uint32_t)lo;
+}
+__device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        uint64_t o = shfl_xor_u64(v, m);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+        uint64_t o = shfl_xor_u64(v, m);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+__device__ __forceinline__ float thr_of(float r, float onep) {
+    // r (1 + eps) of Algorithm 1; infinity stays infinity
+    if (__builtin_isinf(r) || __builtin_isinf(onep)) return __builtin_inff();
+    return __fmul_rn(r, onep);
+}
+
+// ---------------------------------------------------------------- FP8 E4M3 decode
+// Exact value of an OCP E4M3 code: exponent field 0 -> m * 2^-9, else
+// (8 + m) * 2^(e - 10). Code 0x7f/0xff (NaN) never occurs in an encoded store.
+__device__ __forceinline__ float e4m3_value(uint32_t c) {
+    uint32_t e = (c >> 3) & 15u, m = c & 7u;
+    float v = e == 0 ? (float)m * 0.001953125f : __builtin_ldexpf((float)(8u + m), (int)e - 10);
+    return (c & 0x80u) ? -v : v;
+}
+
+// ---------------------------------------------------------------- chunk loads
+// Loads chunk `ch` (dims 4ch..4ch+3) of row `id` decoded to FP32.
+template <int DT>
+__device__ __forceinline__ float4 load_chunk(const SearchParams &P, int32_t id, int ch, float sc) {
+    if constexpr (DT == DT_F32) {
+        const float4 *r = reinterpret_cast<const float4 *>(
+            static_cast<const float *>(P.vec) + (int64_t)id * P.vstride);
+        return r[ch];
+    } else if constexpr (DT == DT_BF16) {
+        const uint2 *r = reinterpret_cast<const uint2 *>(
+            static_cast<const uint16_t *>(P.vec) + (int64_t)id * P.vstride);
+        uint2 u = r[ch];
+        return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
+                           __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
+    } else {
+        const uint32_t *r = reinterpret_cast<const uint32_t *>(
+            static_cast<const uint8_t *>(P.vec) + (int64_t)id * P.vstride);
+        uint32_t u = r[ch];
+        return make_float4(__fmul_rn(sc, e4m3_value(u & 0xffu)),
+                           __fmul_rn(sc, e4m3_value((u >> 8) & 0xffu)),
+                           __fmul_rn(sc, e4m3_value((u >> 16) & 0xffu)),
+                           __fmul_rn(sc, e4m3_value(u >> 24)));
+    }
+}
+
+template <int METRIC>
+__device__ __forceinline__ float acc_chunk(float acc, float4 x, float4 q) {
+    if constexpr (METRIC == DEG_METRIC_L2) {
+        float t;
+        t = __fsub_rn(x.x, q.x); acc = __fmaf_rn(t, t, acc);
+        t = __fsub_rn(x.y, q.y); acc = __fmaf_rn(t, t, acc);
+        t = __fsub_rn(x.z, q.z); acc = __fmaf_rn(t, t, acc);
+        t = __fsub_rn(x.w, q.w); acc = __fmaf_rn(t, t, acc);
+    } else {
+        acc = __fmaf_rn(x.x, q.x, acc);
+        acc = __fmaf_rn(x.y, q.y, acc);
+        acc = __fmaf_rn(x.z, q.z, acc);
+        acc = __fmaf_rn(x.w, q.w, acc);
+    }
+    return acc;
+}
+
+// xor butterfly over the 32 lanes of a half-wave; pairs (p, p+w) as the tree does
+__device__ __forceinline__ float half_reduce(float a) {
+    a = __fadd_rn(a, __shfl_xor(a, 16, 32));
+    a = __fadd_rn(a, __shfl_xor(a, 8, 32));
+    a = __fadd_rn(a, __shfl_xor(a, 4, 32));
+    a = __fadd_rn(a, __shfl_xor(a, 2, 32));
+    a = __fadd_rn(a, __shfl_xor(a, 1, 32));
+    return a;
+}
+
+// Distances of up to 64 candidates; lane j < ncand holds candidate j in `cid`
+// (LDS, already written). Result for candidate j is returned in lane j.
+// Rounds of G candidates per half-wave are loaded before any is reduced so
+// that many row loads are in flight. F32ROWS reads the FP32 rows (rerank)
+// instead of the traversal store.
+template <int DT, int METRIC, int QCH, bool F32ROWS = false>
+__device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
+                                            const int32_t *cid, float *cdist, int ncand,
+                                            int nch, bool mask_tail) {
+    constexpr int G = QCH <= 1 ? 8 : (QCH <= 2 ? 4 : (QCH <= 4 ? 2 : 1));
+    const int lane = lane_id();
+    const int half = lane >> 5, p = lane & 31;
+    const int rounds = (ncand + 1) >> 1;
+    for (int t0 = 0; t0 < rounds; t0 += G) {
+        float4 xv[G][QCH];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            int j = 2 * (t0 + g) + half;
+            bool ok = (t0 + g) < rounds && j < ncand;
+            int32_t id = ok ? cid[j] : 0;
+            float sc = 1.0f;
+            if constexpr (DT == DT_FP8 && !F32ROWS) {
+                if (ok) sc = P.scale[id];
+            }
+#pragma unroll
+            for (int c = 0; c < QCH; ++c) {
+                int ch = p + 32 * c;
+                if (ok && ch < nch) {
+                    if constexpr (F32ROWS) {
+                        const float4 *r =
+                            reinterpret_cast<const float4 *>(P.f32 + (int64_t)id * P.f32_stride);
+                        xv[g][c] = r[ch];
+                    } else {
+                        xv[g][c] = load_chunk<DT>(P, id, ch, sc);
+                    }
+                } else {
+                    xv[g][c] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            int j = 2 * (t0 + g) + half;
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < QCH; ++c) {
+                float4 x = xv[g][c];
+                if (mask_tail) {
+                    int base = 4 * (p + 32 * c);
+                    if (base + 0 >= P.dim) x.x = 0.f;
+                    if (base + 1 >= P.dim) x.y = 0.f;
+                    if (base + 2 >= P.dim) x.z = 0.f;
+                    if (base + 3 >= P.dim) x.w = 0.f;
+                }
+                acc = acc_chunk<METRIC>(acc, x, qv[c]);
+            }
+            acc = half_reduce(acc);
+            if (METRIC == DEG_METRIC_IP) acc = __fsub_rn(1.0f, acc);
+            if (p == 0 && (t0 + g) < rounds && j < ncand) cdist[j] = acc;
+        }
+    }
+    wave_sync();
+    return lane < ncand ? cdist[lane] : 0.0f;
+}
+
+// ---------------------------------------------------------------- visited set
+struct Visited {
+    int32_t *htab;  // LDS
+    int32_t *gtab;  // workspace
+    int H, hshift, Hg, hgshift;
+    int count;      // wave-uniform
+    bool spilled;   // wave-uniform
+};
+
+__device__ __forceinline__ uint32_t hash_slot(int32_t id, int shift) {
+    return ((uint32_t)id * 0x9E3779B1u) >> shift;
+}
+
+// Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the set.
+__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
+    bool isnew = false;
+    if (act) {
+        if (!V.spilled) {
+            uint32_t msk = (uint32_t)V.H - 1u;
+            uint32_t s = hash_slot(id, V.hshift);
+            for (;;) {
+                int32_t old = atomicCAS(&V.htab[s], -1, id);
+                if (old == -1) { isnew = true; break; }
+                if (old == id) break;
+                s = (s + 1u) & msk;
+            }
+        } else {
+            uint32_t msk = (uint32_t)V.Hg - 1u;
+            uint32_t s = hash_slot(id, V.hgshift);
+            for (;;) {
+                int32_t old = atomicCAS(&V.gtab[s], -1, id);
+                if (old == -1) { isnew = true; break; }
+                if (old == id) break;
+                s = (s + 1u) & msk;
+            }
+        }
+    }
+    return isnew;
+}
+
+// Moves the LDS table to the workspace table (cleared first).
+__device__ __forceinline__ void visit_spill(Visited &V) {
+    const int lane = lane_id();
+    for (int i = lane; i < V.Hg; i += WAVE) V.gtab[i] = -1;
+    __threadfence();
+    wave_sync();
+    V.spilled = true;
+    for (int i = lane; i < V.H; i += WAVE) {
+        int32_t id = V.htab[i];
+        if (id >= 0) {
+            uint32_t msk = (uint32_t)V.Hg - 1u;
+            uint32_t s = hash_slot(id, V.hgshift);
+            for (;;) {
+                int32_t old = atomicCAS(&V.gtab[s], -1, id);
+                if (old == -1 || old == id) break;
+                s = (s + 1u) & msk;
+            }
+        }
+    }
+    __threadfence();
+    wave_sync();
+}
+
+}  // namespace degk

@@ -1,0 +1,241 @@
+"""GPU parity of the HIP search (through the C ABI) with the CPU oracle.
+
+The plain FP32 path must return the oracle's ids and distances bit for bit,
+with the same hop and evaluation counts (both use the fixed C32x4 reduction
+and the (distance, id) order)."""
+import json
+import sys
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+GOLD = Path(__file__).resolve().parent / "golden"
+DATA = Path(__file__).resolve().parent.parent / "data"
+
+
+def say(*a):
+    print("[gpu-test]", *a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_2307_10479_amd import api
+    api.lib()
+    return api
+
+
+_G = {}
+
+
+def graph(n, m, d, kind="int", metric=oracle.L2, seed=0):
+    key = (n, m, d, kind, metric, seed)
+    if key not in _G:
+        if kind == "int":
+            x = synth.small_int(seed, n, m, hi=64)
+        elif kind == "unit":
+            x = synth.small_unit(seed, n, m)
+        else:
+            x = synth.small_float(seed, n, m)
+        adj, w, _ = oracle.build_graph(x, d, metric, k_ext=2 * d, eps_ext=0.2, k_opt=d)
+        _G[key] = (x, adj)
+    return _G[key]
+
+
+def queries_for(kind, seed, nq, m):
+    if kind == "int":
+        return synth.small_int(seed, nq, m, hi=64)
+    if kind == "unit":
+        return synth.small_unit(seed, nq, m)
+    return synth.small_float(seed, nq, m)
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t if dtype is None else t.to(dtype)
+
+
+BIG_L = 4096  # parity sweeps give both sides the same capacity of S
+
+
+def run_gpu(A, x, adj, q, seeds, k, eps, metric=oracle.L2, dtype="f32", **opts):
+    opts.setdefault("queue_cap", BIG_L)
+    store = A.VectorStore(dev(x), dtype, metric)
+    g = A.DeviceGraph(dev(adj))
+    ids, ds, st = A.search(store, g, dev(q), dev(np.asarray(seeds, np.int32)), k, eps, **opts)
+    torch.cuda.synchronize()
+    return ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()
+
+
+def assert_parity(got, ref, what):
+    ids, ds, st = got
+    rids, rds, rst = ref
+    bad = np.nonzero((ids != rids).any(1) | (st[:, 0] != rst[:, 0]) | (st[:, 1] != rst[:, 1]))[0]
+    if len(bad):
+        i = bad[0]
+        raise AssertionError("%s: %d/%d queries differ; first q=%d gpu ids %s hops/evals %s | oracle %s %s"
+                             % (what, len(bad), ids.shape[0], i, ids[i][:8], st[i][:2], rids[i][:8], rst[i][:2]))
+    same = (ds == rds) | (np.isinf(ds) & np.isinf(rds))
+    assert same.all(), "%s: distances differ" % what
+
+
+# ---------------------------------------------------------------- tiny hand-traced case
+def test_golden_toy(A):
+    g = json.loads((GOLD / "alg1_toy.json").read_text())
+    adj = np.array(g["adj"], np.int32)
+    for c in g["cases"]:
+        pts = np.array(c["points"], np.float32).reshape(-1, 1)
+        say("toy", c["k"], c["eps"])
+        store = A.VectorStore(dev(pts), "f32")
+        G = A.DeviceGraph(dev(adj))
+        if "query_vertex" in c:
+            ids, ds, st = A.search_indexed(store, G, dev(np.array([c["query_vertex"]], np.int32)), c["k"], c["eps"])
+        else:
+            ids, ds, st = A.search(store, G, dev(np.array([[c["query"]]], np.float32)),
+                                   dev(np.array([c["seeds"]], np.int32)), c["k"], c["eps"])
+        torch.cuda.synchronize()
+        assert ids.cpu().numpy()[0].tolist() == c["ids"], c["trace"]
+        assert ds.cpu().numpy()[0].tolist() == [float(v) for v in c["dists"]]
+        st = st.cpu().numpy()[0]
+        assert st[0] == c["hops"] and st[1] == c["evals"], c["trace"]
+
+
+# ---------------------------------------------------------------- parity sweeps
+@pytest.mark.parametrize("kind,metric,m", [("int", oracle.L2, 24), ("float", oracle.L2, 37),
+                                           ("unit", oracle.IP, 100), ("float", oracle.L2, 300)])
+@pytest.mark.parametrize("k,eps", [(1, 0.0), (10, 0.0), (10, 0.1), (64, 0.05), (65, 0.2), (100, 0.1)])
+def test_parity_small_graphs(A, kind, metric, m, k, eps):
+    x, adj = graph(1500, m, 30 if m < 300 else 20, kind, metric)
+    q = queries_for(kind, 55, 150, m)
+    say("parity", kind, metric, m, k, eps)
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), k, eps, metric)
+    ref = oracle.range_search(x, adj, q, [0], k, eps, metric, cap_L=BIG_L)
+    assert_parity(got, ref, "parity %s m=%d k=%d eps=%g" % (kind, m, k, eps))
+
+
+@pytest.mark.parametrize("k", [128, 256, 300, 512])
+def test_parity_large_k(A, k):
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 56, 60, 24)
+    say("large k", k)
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), k, 0.05)
+    ref = oracle.range_search(x, adj, q, [0], k, 0.05, cap_L=BIG_L)
+    assert_parity(got, ref, "k=%d" % k)
+
+
+def test_parity_exhaustive_and_padding(A):
+    x, adj = graph(300, 16, 6)
+    q = queries_for("int", 57, 40, 16)
+    say("exhaustive")
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), 40, float("inf"))
+    ref = oracle.range_search(x, adj, q, [0], 40, float("inf"), cap_L=BIG_L)
+    assert_parity(got, ref, "eps=inf")
+    assert (got[2][:, 1] == 300).all()
+    # k larger than N: padded rows
+    d = 4
+    xs = synth.small_int(9, d + 1, 5, hi=10)
+    adjs, _, _ = oracle.build_graph(xs, d)
+    got = run_gpu(A, xs, adjs, xs[:3], [[1]] * 3, 8, 0.0)
+    ref = oracle.range_search(xs, adjs, xs[:3], [1], 8, 0.0)
+    assert_parity(got, ref, "k>N")
+    assert (got[0][:, 5:] == -1).all()
+
+
+def test_parity_multi_seed(A):
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 58, 100, 24)
+    seeds = synth.rng(58).choice(1500, size=(100, 5), replace=False).astype(np.int32)
+    seeds = np.stack([synth.rng(100 + i).choice(1500, size=5, replace=False) for i in range(100)]).astype(np.int32)
+    say("multi seed")
+    got = run_gpu(A, x, adj, q, seeds, 10, 0.1)
+    ref = oracle.range_search(x, adj, q, seeds, 10, 0.1, cap_L=BIG_L)
+    assert_parity(got, ref, "5 seeds")
+
+
+@pytest.mark.parametrize("L", [8, 20, 100])
+def test_parity_queue_capacity(A, L):
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 59, 100, 24)
+    say("capacity", L)
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), 20, 0.2, queue_cap=L)
+    ref = oracle.range_search(x, adj, q, [0], 20, 0.2, cap_L=L)
+    assert_parity(got, ref, "L=%d" % L)
+    ovf = (got[2][:, 2] & A.FLAG_QUEUE_OVERFLOW) != 0
+    assert (ovf == (ref[2][:, 3] != 0)).all()
+
+
+def test_parity_hash_spill(A):
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 60, 100, 24)
+    say("hash spill")
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), 50, 0.3, hash_slots=256)
+    ref = oracle.range_search(x, adj, q, [0], 50, 0.3, cap_L=BIG_L)
+    assert_parity(got, ref, "H=256")
+    assert ((got[2][:, 2] & A.FLAG_HASH_SPILL) != 0).any()
+
+
+def test_parity_indexed(A):
+    x, adj = graph(1500, 100, 30, "unit", oracle.IP)
+    qids = synth.rng(61).choice(1500, size=200, replace=False).astype(np.int32)
+    say("indexed")
+    store = A.VectorStore(dev(x), "f32", oracle.IP)
+    G = A.DeviceGraph(dev(adj))
+    for k, eps in ((10, 0.0), (100, 0.1)):
+        ids, ds, st = A.search_indexed(store, G, dev(qids), k, eps, queue_cap=BIG_L)
+        torch.cuda.synchronize()
+        ref = oracle.range_search_indexed(x, adj, qids, k, eps, oracle.IP, cap_L=BIG_L)
+        assert_parity((ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()), ref, "indexed k=%d" % k)
+        assert not (ids.cpu().numpy() == qids[:, None]).any()
+
+
+def test_parity_cfg1_full(A):
+    p = DATA / "cfg1.deg"
+    if not p.exists():
+        pytest.skip("data/cfg1.deg not built (python -m oracle.build_graph --cfg 1)")
+    from synth.io import load_graph
+    adj, metric, _ = load_graph(p)
+    base, q = synth.cfg1()
+    for eps in (0.0, 0.1):
+        say("cfg1", eps)
+        got = run_gpu(A, base, adj, q, [[0]] * len(q), 10, eps)
+        ref = oracle.range_search(base, adj, q, [0], 10, eps, cap_L=BIG_L)
+        assert_parity(got, ref, "cfg1 eps=%g" % eps)
+
+
+def test_default_capacity(A):
+    # with the library's default L: where no live candidate was dropped, the result
+    # equals the unbounded oracle; where one was, the overflow flag says so
+    x, adj = graph(1500, 37, 30, "float", oracle.L2)
+    q = queries_for("float", 55, 150, 37)
+    say("default capacity")
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), 65, 0.2, queue_cap=0)
+    ref = oracle.range_search(x, adj, q, [0], 65, 0.2)
+    ok = (got[2][:, 2] & A.FLAG_QUEUE_OVERFLOW) == 0
+    assert ok.all()
+    assert_parity(got, ref, "default L")
+
+
+def test_bad_ids_flagged(A):
+    x, adj = graph(300, 16, 6)
+    q = queries_for("int", 62, 4, 16)
+    say("bad ids")
+    got = run_gpu(A, x, adj, q, [[0], [299], [300], [-1]], 5, 0.0)
+    assert (got[2][:2, 2] & A.FLAG_BAD_ID == 0).all()
+    assert (got[2][2:, 2] & A.FLAG_BAD_ID != 0).all()
+    assert (got[0][2:] == -1).all()
+
+
+def test_deterministic(A):
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 63, 300, 24)
+    say("determinism")
+    a = run_gpu(A, x, adj, q, [[0]] * len(q), 10, 0.1)
+    b = run_gpu(A, x, adj, q, [[0]] * len(q), 10, 0.1)
+    for u, v in zip(a, b):
+        assert (u == v).all()
