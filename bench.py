@@ -1,0 +1,260 @@
+#!/usr/bin/env python3
+"""Benchmark: QPS at recall@10 >= 0.95 of the DEG range search on one MI355X.
+
+Workload (default): 1,000,000 x 128 integer-valued Gaussian mixture (1,000
+clusters), squared L2, DEG of degree 30 built by the CPU oracle, 10,000
+held-out queries, k = 10, seed = the medoid vertex. The graph, the ground
+truth (exact FP64 kNN) and the medoid come from `python -m oracle.build_graph
+--cfg 2`; the vectors are regenerated from their seeds.
+
+Methods, each at the smallest swept eps whose recall@10 >= target:
+  P   plain FP32 traversal (bit-identical to the oracle's Algorithm 1)
+  B   BF16 traversal + exact FP32 rerank of the pool
+  BL  B + learned early stop (MLP trained here on plain-search traces by the
+      library's own kernels; tau calibrated on held-out training queries)
+A step is one pass of method BL over all queries (one persistent launch).
+The JSON line reports BL's QPS as `value`, P and B alongside, the search
+kernel's achieved algorithmic HBM bandwidth against the 8 TB/s peak, and the
+oracle's search timed on this host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+EPS_SWEEP = [0.0, 0.01, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4]
+HBM_PEAK_GBS = 8000.0
+WORKLOADS = {
+    "cfg2": dict(desc="1,000,000 x 128 integer Gaussian mixture (1,000 clusters), squared L2, "
+                      "DEG d=30, 10,000 queries", n_train=200_000),
+    "cfg1": dict(desc="10,000 x 128 integer Gaussian mixture (64 clusters), squared L2, DEG d=30, "
+                      "1,000 queries", n_train=50_000),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def load_workload(name):
+    import synth
+    from synth.io import load_graph
+    w = WORKLOADS[name]
+    gp = ROOT / "data" / ("%s.deg" % name)
+    gtp = ROOT / "data" / ("%s.gt.npz" % name)
+    mp = ROOT / "data" / ("%s.meta.json" % name)
+    if not gp.exists() or not gtp.exists():
+        sys.exit("bench: %s or %s missing; build them with `python -m oracle.build_graph --cfg %s`"
+                 % (gp, gtp, name[-1]))
+    t0 = time.time()
+    if name == "cfg2":
+        base, q, train = synth.cfg2(n_train=w["n_train"])
+    else:
+        base, q, train = synth.cfg1(n_train=w["n_train"])
+    adj, metric, _ = load_graph(gp)
+    gt = np.load(gtp)["ids"]
+    meta = json.loads(mp.read_text()) if mp.exists() else {}
+    log("loaded %s: base %s, queries %s, train %s, graph %s in %.1fs"
+        % (name, base.shape, q.shape, train.shape, adj.shape, time.time() - t0))
+    return base, q, train, adj, metric, gt, meta
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
+    ap.add_argument("--k", type=int, default=10)
+    ap.add_argument("--recall", type=float, default=0.95)
+    ap.add_argument("--stop-interval", type=int, default=2)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", default="", help="profile mode: time just this method (P, B or BL)")
+    a = ap.parse_args(argv)
+    if a.gpus != 1:
+        print("bench.py: this build measures one GPU; the search shards by replicating the index "
+              "and splitting the queries, but only --gpus 1 is measured here", file=sys.stderr)
+        return 2
+
+    import torch
+
+    import synth  # noqa: F401
+    from paper_2307_10479_amd import api, metrics, stop
+
+    api.lib()
+    torch.cuda.set_device(0)
+    base, q, train, adj, metric, gt, meta = load_workload(a.workload)
+    nq, m = q.shape
+    n, d = adj.shape
+    k = a.k
+
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    t0 = time.time()
+    xb = dev(base)
+    s32 = api.VectorStore(xb, "f32", metric)
+    s16 = api.VectorStore(xb, "bf16", metric)
+    G = api.DeviceGraph(dev(adj))
+    Q = dev(q)
+    seed = api.medoid(xb, metric)
+    if meta.get("medoid") is not None and meta["medoid"] != seed:
+        log("note: device medoid %d differs from the oracle's %d" % (seed, meta["medoid"]))
+    seeds = torch.full((nq, 1), seed, dtype=torch.int32, device="cuda")
+    torch.cuda.synchronize()
+    log("device stores ready in %.1fs; seed %d" % (time.time() - t0, seed))
+
+    def run(method, eps, model=None, out=None):
+        store = s32 if method == "P" else s16
+        return api.search(store, G, Q, seeds, k, eps, out=out,
+                          stop=model if method == "BL" else None)
+
+    def sweep(method, model=None):
+        rows = []
+        for eps in EPS_SWEEP:
+            ids, ds, st = run(method, eps, model)
+            torch.cuda.synchronize()
+            r = metrics.recall_at_k(ids.cpu().numpy(), gt, 10)
+            stn = st.cpu().numpy()
+            rows.append(dict(eps=eps, recall=r, hops=float(stn[:, 0].mean()),
+                             evals=float(stn[:, 1].mean()),
+                             stopped=float(((stn[:, 2] & api.FLAG_LEARNED_STOP) != 0).mean())))
+            if r >= a.recall:
+                break
+        ok = [x for x in rows if x["recall"] >= a.recall]
+        return (ok[0] if ok else rows[-1]), rows
+
+    # ---- plain and BF16 operating points
+    opP, rowsP = sweep("P")
+    opB, rowsB = sweep("B")
+    log("P  sweep:", [(x["eps"], round(x["recall"], 4), round(x["evals"], 1)) for x in rowsP])
+    log("B  sweep:", [(x["eps"], round(x["recall"], 4), round(x["evals"], 1)) for x in rowsB])
+
+    # ---- learned stop: traces, training, calibration (all on the GPU)
+    t1 = time.time()
+    ntr = train.shape[0]
+    nhold = min(10_000, ntr // 10)
+    Tq = dev(train[: ntr - nhold])
+    Hq = dev(train[ntr - nhold:])
+    tseeds = torch.full((Tq.shape[0], 1), seed, dtype=torch.int32, device="cuda")
+    hseeds = torch.full((nhold, 1), seed, dtype=torch.int32, device="cuda")
+    train_eps = sorted(set([0.0, opB["eps"], min(0.4, opB["eps"] * 2 + 0.02)]))
+    X, y = stop.collect_traces(s16, G, Tq, tseeds, k, train_eps, interval=a.stop_interval)
+    mean, inv_std = stop.standardise(X)
+    Xs = ((X - mean) * inv_std).contiguous()
+    params, hist = stop.train(Xs, y.contiguous(), epochs=4)
+    tau, cal = stop.calibrate(s16, G, Hq, hseeds, k, opB["eps"], params, mean, inv_std,
+                              a.stop_interval)
+    model = stop.build_model(params, mean, inv_std, tau, a.stop_interval)
+    torch.cuda.synchronize()
+    log("stop model: %d rows (%.2f positive), loss %s, tau %.3f, calibration %s, %.1fs"
+        % (X.shape[0], float(y.mean()), [round(h, 4) for h in hist], tau,
+           [(t, round(g, 4), round(h, 1)) for t, g, h in cal], time.time() - t1))
+    del X, y, Xs, Tq
+    opBL, rowsBL = sweep("BL", model)
+    log("BL sweep:", [(x["eps"], round(x["recall"], 4), round(x["evals"], 1), round(x["stopped"], 3))
+                      for x in rowsBL])
+
+    # ---- timed steps
+    def timed(method, eps, mdl=None):
+        ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
+        ds = torch.empty((nq, k), dtype=torch.float32, device="cuda")
+        st = torch.empty((nq, 4), dtype=torch.int32, device="cuda")
+        out = (ids, ds, st)
+        for _ in range(a.warmup):
+            run(method, eps, mdl, out)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(a.steps):
+            run(method, eps, mdl, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / a.steps
+        stn = st.cpu().numpy()
+        r = metrics.recall_at_k(ids.cpu().numpy(), gt, 10)
+        return ms, stn, r
+
+    res = {}
+    for name, op, mdl in (("P", opP, None), ("B", opB, None), ("BL", opBL, model)):
+        if a.only and name != a.only:
+            continue
+        ms, stn, r = timed(name, op["eps"], mdl)
+        row_bytes = 4 * m if name == "P" else 2 * m
+        evals = int(stn[:, 1].astype(np.int64).sum())
+        hops = int(stn[:, 0].astype(np.int64).sum())
+        rerank = 0 if name == "P" else nq * k * 4 * m
+        alg_bytes = evals * row_bytes + hops * 4 * d + nq * (4 * m + 8 * k) + rerank
+        res[name] = dict(eps=op["eps"], recall=r, ms=ms, qps=nq / (ms / 1e3),
+                         hops=hops / nq, evals=evals / nq, alg_bytes=alg_bytes,
+                         gbs=alg_bytes / (ms / 1e3) / 1e9)
+        log("%-2s eps %.3f recall %.4f  %.3f ms/step  %.0f QPS  hops %.1f evals %.1f  %.0f GB/s"
+            % (name, op["eps"], r, ms, res[name]["qps"], hops / nq, evals / nq, res[name]["gbs"]))
+
+    head = res.get("BL") or next(iter(res.values()))
+    # ---- CPU baseline: the oracle's Algorithm 1 on a bounded sample, all host threads
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        thr = oracle.nthreads_default()
+        sample = min(nq, 500)
+        t2 = time.time()
+        oracle.range_search(base, adj, q[:sample], [seed], k, opP["eps"], metric, nthreads=thr)
+        dt = time.time() - t2
+        if dt < a.cpu_seconds / 3 and sample < nq:
+            sample = int(min(nq, sample * a.cpu_seconds / max(dt, 1e-3)))
+            t2 = time.time()
+            oracle.range_search(base, adj, q[:sample], [seed], k, opP["eps"], metric, nthreads=thr)
+            dt = time.time() - t2
+        cpu = dict(value=sample / dt, unit="queries/s", cores=thr, kind="oracle",
+                   sample="first %d of the %d queries, plain FP32 Algorithm 1 at eps=%g, k=%d"
+                          % (sample, nq, opP["eps"], k))
+        log("cpu oracle: %d queries in %.1fs on %d threads = %.0f QPS" % (sample, dt, thr, sample / dt))
+
+    out = {
+        "metric": "QPS @ recall@10>=0.95, 1M x 128 L2: BF16+learned-stop vs plain FP32"
+                  if a.workload == "cfg2" else "QPS @ recall@10>=0.95 (%s)" % a.workload,
+        "value": head["qps"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "%s: %s" % (a.workload, WORKLOADS[a.workload]["desc"]),
+            "method": "BL: BF16 traversal + FP32 rerank + learned early stop",
+            "k": k, "eps": head["eps"], "recall@10": round(head["recall"], 5),
+            "tau": tau, "stop_interval": a.stop_interval,
+            "hops_per_query": round(head["hops"], 2), "evals_per_query": round(head["evals"], 2),
+            "plain_fp32": {kk: (round(v, 5) if isinstance(v, float) else v)
+                           for kk, v in res.get("P", {}).items()},
+            "bf16_rerank": {kk: (round(v, 5) if isinstance(v, float) else v)
+                            for kk, v in res.get("B", {}).items()},
+            "bl_over_plain_qps": (res["BL"]["qps"] / res["P"]["qps"]) if "BL" in res and "P" in res else None,
+        },
+        "roofline": {
+            "bound": "hbm", "achieved": round(head["gbs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(head["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+        },
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
