@@ -114,7 +114,7 @@ typedef struct {
     float *trace;       /* device; non-NULL = write stop-predictor training rows */
     int64_t trace_rows_per_query; /* rows per query in `trace` (each 20 floats) */
     int32_t trace_interval;       /* hops between two trace rows */
-    int32_t waves_per_block;      /* 0 = autotuned */
+    int32_t waves_per_cu;         /* resident waves per CU of the persistent grid; 0 = tuned */
 } deg_search_opts;
 
 /*

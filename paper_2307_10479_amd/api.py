@@ -59,7 +59,7 @@ class DegSearchOpts(C.Structure):
     _fields_ = [("queue_cap", C.c_int32), ("hash_slots", C.c_int32), ("k_pool", C.c_int32),
                 ("rerank", C.c_int32), ("stop", C.POINTER(DegStopModel)), ("trace", C.c_void_p),
                 ("trace_rows_per_query", C.c_int64), ("trace_interval", C.c_int32),
-                ("waves_per_block", C.c_int32)]
+                ("waves_per_cu", C.c_int32)]
 
 
 class DegQueryDesc(C.Structure):
@@ -226,7 +226,7 @@ class StopModel:
 
 
 def _opts(queue_cap=0, hash_slots=0, k_pool=0, rerank=False, stop: StopModel | None = None,
-          trace=None, trace_rows=0, trace_interval=0, waves_per_block=0):
+          trace=None, trace_rows=0, trace_interval=0, waves_per_cu=0):
     o = DegSearchOpts()
     o.queue_cap, o.hash_slots, o.k_pool, o.rerank = int(queue_cap), int(hash_slots), int(k_pool), int(bool(rerank))
     keep = None
@@ -237,7 +237,7 @@ def _opts(queue_cap=0, hash_slots=0, k_pool=0, rerank=False, stop: StopModel | N
         o.trace = trace.data_ptr()
         o.trace_rows_per_query = int(trace_rows)
         o.trace_interval = int(trace_interval)
-    o.waves_per_block = int(waves_per_block)
+    o.waves_per_cu = int(waves_per_cu)
     return o, keep
 
 

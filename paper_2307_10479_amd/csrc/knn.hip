@@ -220,8 +220,6 @@ template <int METRIC, int QCH>
 __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *keys = reinterpret_cast<uint64_t *>(smem);       // nslices * kc
-    int32_t *cid = reinterpret_cast<int32_t *>(keys + P.nslices * P.kc);
-    float *cdist = reinterpret_cast<float *>(cid + WAVE);
     const int lane = lane_id(), p = lane & 31;
     const int64_t qi = blockIdx.x;
     if (qi >= P.nq) return;
@@ -247,12 +245,10 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P) {
         for (int b = 0; b < c; b += WAVE) {
             int nc = min(WAVE, c - b);
             int32_t id = lane < nc ? key_id(lst[b + lane]) : 0;
-            cid[lane] = id;
-            wave_sync();
-            float d = batch_dist<DT_F32, METRIC, QCH, true>(SP, qv, cid, cdist, nc, nch, mask_tail);
+            uint64_t msk = nc == WAVE ? ~0ull : ((1ull << nc) - 1ull);
+            float d = batch_dist<DT_F32, METRIC, QCH, true>(SP, qv, id, msk, nch, mask_tail);
             if (lane < nc) keys[tot + lane] = make_key(d, id);
             tot += nc;
-            wave_sync();
         }
     }
     wave_sync();

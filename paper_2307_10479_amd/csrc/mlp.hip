@@ -181,7 +181,7 @@ __global__ void mlp_forward_f32(const float *__restrict__ P, const float *__rest
 // One wave per row with the same routine the search uses.
 __global__ void __launch_bounds__(64) mlp_forward_bf16_kernel(const uint16_t *W, const float *X,
                                                               int64_t B, float *out) {
-    __shared__ float hbuf[64];
+    __shared__ __align__(16) float hbuf[64];
     for (int64_t row = blockIdx.x; row < B; row += gridDim.x) {
         float f[MLP_IN];
 #pragma unroll

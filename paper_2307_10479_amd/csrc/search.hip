@@ -13,11 +13,11 @@ namespace degk {
 
 __global__ void reset_counter_kernel(int32_t *c) { *c = 0; }
 
-static KernelFn pick_kernel(int dt, int metric, int qch, int rreg) {
+static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, bool feat) {
     switch (dt) {
-        case DT_F32: return pick_kernel_f32(metric, qch, rreg);
-        case DT_BF16: return pick_kernel_bf16(metric, qch, rreg);
-        default: return pick_kernel_fp8(metric, qch, rreg);
+        case DT_F32: return pick_kernel_f32(metric, qch, rreg, feat);
+        case DT_BF16: return pick_kernel_bf16(metric, qch, rreg, feat);
+        default: return pick_kernel_fp8(metric, qch, rreg, feat);
     }
 }
 
@@ -78,7 +78,7 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     c.qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
     int L = (o && o->queue_cap > 0) ? o->queue_cap : (8 * kp > 512 ? 8 * kp : 512);
     c.L = L;
-    c.scap = L > kp ? L : kp;
+    c.scap = ((L > kp ? L : kp) + 63) / 64 * 64;
     const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);
     int H = (o && o->hash_slots) ? o->hash_slots : (t ? t->hash_slots : (kp <= 32 ? 2048 : 4096));
     c.H = H;
@@ -87,8 +87,9 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     while (Hg < 4 * H) Hg <<= 1;
     c.Hg = Hg;
     c.hgshift = 32 - ilog2(Hg);
-    c.lds = 4 * (size_t)H + 8 * (size_t)(c.scap + 64) + 8 * 64 * (size_t)c.rreg + 8 * 64 + 4 * 64 * 3;
-    c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg);
+    c.lds = 4 * (size_t)H + 8 * (size_t)(c.scap + 64) + 8 * 64 * (size_t)c.rreg + 4 * 64;
+    const bool feat = o && (o->stop || o->trace);
+    c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg, feat);
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(c.fn), 64,
                                                      c.lds) != hipSuccess || nb < 1)
@@ -96,7 +97,7 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     int cus = deg_device_cu_count();
     int64_t grid = (int64_t)nb * cus;
     if (t && t->waves_per_cu > 0 && t->waves_per_cu < nb) grid = (int64_t)t->waves_per_cu * cus;
-    if (o && o->waves_per_block > 0) grid = (int64_t)o->waves_per_block * cus;
+    if (o && o->waves_per_cu > 0) grid = (int64_t)o->waves_per_cu * cus;
     if (grid > nq) grid = nq;
     if (grid < 1) grid = 1;
     c.grid = (int)grid;

@@ -2,5 +2,7 @@
 #include "search_impl.h"
 
 namespace degk {
-KernelFn pick_kernel_fp8(int metric, int qch, int rreg) { return pick_m<DT_FP8>(metric, qch, rreg); }
+KernelFn pick_kernel_fp8(int metric, int qch, int rreg, bool feat) {
+    return pick_m<DT_FP8>(metric, qch, rreg, feat);
+}
 }  // namespace degk

@@ -56,36 +56,35 @@ __device__ __forceinline__ uint64_t r_at(const uint64_t (&R)[RREG], int i) {
     return read_lane_u64(v, i & 63);
 }
 
-// Merges the offered candidate keys into the sorted result list (top-kp by
-// key). `total` counts every key ever offered; once it exceeds kp the radius
-// r is the kp-th distance (Algorithm 1: r changes when R overflows).
-// Returns true if an accepted key landed in the first `t10` positions.
+// Merges the offered candidate keys (lanes set in `om`, key `ck`) into the
+// sorted result list (top-kp by key). `total` counts every key ever offered;
+// once it exceeds kp the radius r is the kp-th distance (Algorithm 1: r
+// changes when R overflows). Returns true if an accepted key landed in the
+// first `t10` positions; `naccepted` gets the number of accepted keys.
 template <int RREG>
 __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &total, bool &ovf,
-                                        int kp, uint64_t ck, bool offer, uint64_t *kst,
-                                        uint64_t *mbuf, int t10, int &naccepted) {
+                                        int kp, uint64_t ck, uint64_t om, uint64_t *mbuf, int t10,
+                                        int &naccepted) {
     const int lane = lane_id();
-    uint64_t rlast = ovf ? r_at<RREG>(R, kp - 1) : KEY_MAX;
-    uint64_t om = ballot(offer);
-    bool acc = offer && ck < rlast;
+    const uint64_t rlast = ovf ? r_at<RREG>(R, kp - 1) : KEY_MAX;
+    const bool offer = (om >> lane) & 1ull;
+    const bool acc = offer && ck < rlast;
     uint64_t am = ballot(acc);
-    int na = __popcll(am);
+    const int na = __popcll(am);
     if (!ovf) {
         total += __popcll(om);
         if (total > kp) ovf = true;
     }
     naccepted = na;
     if (na == 0) return false;
-    if (acc) kst[prefix_in(am)] = ck;
-    wave_sync();
-    uint64_t ak = lane < na ? kst[lane] : KEY_MAX;
     int rank_new = 0, myposR = 0;
     int cntR[RREG];
 #pragma unroll
     for (int r = 0; r < RREG; ++r) cntR[r] = 0;
-    for (int t = 0; t < na; ++t) {
-        uint64_t kt = kst[t];
-        rank_new += (kt < ak) ? 1 : 0;
+    for (uint64_t m = am; m; m &= m - 1) {
+        const int t = (int)__builtin_ctzll(m);
+        const uint64_t kt = read_lane_u64(ck, t);
+        rank_new += (kt < ck) ? 1 : 0;
         int posR = 0;
 #pragma unroll
         for (int r = 0; r < RREG; ++r) {
@@ -102,9 +101,9 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
             if (pos < kp) mbuf[pos] = R[r];
         }
     }
-    int newpos = myposR + rank_new;
-    if (lane < na && newpos < kp) mbuf[newpos] = ak;
-    bool top = ballot(lane < na && newpos < t10) != 0;
+    const int newpos = myposR + rank_new;
+    if (acc && newpos < kp) mbuf[newpos] = ck;
+    const bool top = ballot(acc && newpos < t10) != 0;
     rcnt = min(kp, rcnt + na);
     wave_sync();
 #pragma unroll
@@ -117,7 +116,7 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
 }
 
 // ---------------------------------------------------------------- the kernel
-template <int DT, int METRIC, int QCH, int RREG>
+template <int DT, int METRIC, int QCH, int RREG, bool FEAT>
 __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -125,10 +124,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     int32_t *htab = reinterpret_cast<int32_t *>(smem);
     uint64_t *Sq = reinterpret_cast<uint64_t *>(smem + 4 * (size_t)P.H);
     uint64_t *mbuf = Sq + (P.scap + WAVE);
-    uint64_t *kst = mbuf + RREG * WAVE;
-    int32_t *cid = reinterpret_cast<int32_t *>(kst + WAVE);
-    float *cdist = reinterpret_cast<float *>(cid + WAVE);
-    float *hbuf = cdist + WAVE;
+    float *hbuf = reinterpret_cast<float *>(mbuf + RREG * WAVE);
 
     Visited V;
     V.htab = htab;
@@ -231,6 +227,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         float dseed = __builtin_inff(), rprev = __builtin_inff();
         float f_acc_s = 0.f, f_acc_r = 0.f;
         int nrow = 0;
+        int32_t spec_v = -1, spec_nb = -1;  // adjacency row loaded ahead for the likely next pop
 
         // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
         if (!bad_query) {
@@ -241,20 +238,14 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             int cnt = __popcll(nm);
             V.count += cnt;
             evals += cnt;
-            if (isnew) cid[prefix_in(nm)] = seed_l;
-            wave_sync();
-            int32_t cand = lane < cnt ? cid[lane] : -1;
-            float cd = batch_dist<DT, METRIC, QCH>(P, qv, cid, cdist, cnt, nch, mask_tail);
-            uint64_t ck = lane < cnt ? make_key(cd, cand) : KEY_MAX;
+            float cd = batch_dist<DT, METRIC, QCH>(P, qv, seed_l, nm, nch, mask_tail);
+            uint64_t ck = isnew ? make_key(cd, seed_l) : KEY_MAX;
             if (cnt > 0) dseed = key_dist(wave_min_u64(ck));
             int na;
-            bool offer = lane < cnt && cand != vtx;
-            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, offer, kst, mbuf, t10, na);
+            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && seed_l != vtx), mbuf, t10, na);
             r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
-            bool push = lane < cnt;
-            uint64_t pm = ballot(push);
-            if (push) Sq[scnt + prefix_in(pm)] = ck;
-            scnt += __popcll(pm);
+            if (isnew) Sq[scnt + prefix_in(nm)] = ck;
+            scnt += cnt;
             wave_sync();
             while (scnt > P.L) {
                 s_evict_max(Sq, scnt);
@@ -264,27 +255,34 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
 
         // ---- hop loop (Algorithm 1)
         while (scnt > 0) {
-            // s <- argmin of S; S <- S \ {s}
+            // s <- argmin of S; S <- S \ {s}; dead entries (above the threshold) are
+            // dropped when they make up most of S
+            const float thr0 = thr_of(r, onep);
+            const uint32_t othr0 = ord_of(thr0);
             uint64_t mn = KEY_MAX;
-            int mi = -1;
+            int mi = -1, live = 0;
             for (int i = lane; i < scnt; i += WAVE) {
                 uint64_t kk = Sq[i];
+                live += (uint32_t)(kk >> 32) <= othr0 ? 1 : 0;
                 if (kk < mn) { mn = kk; mi = i; }
             }
-            uint64_t gmin = wave_min_u64(mn);
-            uint64_t last = Sq[scnt - 1];
+            const uint64_t gmin = wave_min_u64(mn);
+            const float ds = key_dist(gmin);
+            if (ds > thr0) break;  // too far away: return R
+            const uint64_t last = Sq[scnt - 1];
             wave_sync();
             if (mi >= 0 && mn == gmin) Sq[mi] = last;
             scnt -= 1;
             wave_sync();
-            const float ds = key_dist(gmin);
-            const float thr0 = thr_of(r, onep);
-            if (ds > thr0) break;  // too far away: return R
+            if (scnt > 128) {
+                live = wave_sum_i32(live);
+                if (2 * live < scnt) scnt = s_prune(Sq, scnt, thr0);
+            }
             hops += 1;
 
             // learned stop / trace rows every `interval` hops
-            const bool want_stop = P.stop_w != nullptr && (hops % P.stop_interval) == 0;
-            const bool want_trace = P.trace != nullptr && (hops % P.trace_interval) == 0 &&
+            const bool want_stop = FEAT && P.stop_w != nullptr && (hops % P.stop_interval) == 0;
+            const bool want_trace = FEAT && P.trace != nullptr && (hops % P.trace_interval) == 0 &&
                                     nrow < P.trace_rows;
             if (want_stop || want_trace) {
                 float f[NFEAT];
@@ -338,11 +336,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             // N <- N(G,s) \ C ; C <- C u N
             const int32_t s = key_id(gmin);
             int32_t nb = -1;
-            bool bad = false;
-            if (lane < deg) {
-                nb = P.adj[(int64_t)s * P.astride + lane];
-                if (nb < 0 || (int64_t)nb >= P.n) { bad = true; nb = -1; }
-            }
+            if (lane < deg) nb = (s == spec_v) ? spec_nb : P.adj[(int64_t)s * P.astride + lane];
+            const bool bad = lane < deg && (nb < 0 || (int64_t)nb >= P.n);
+            if (bad) nb = -1;
             if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
             if (!V.spilled && V.count + deg > hlimit) {
                 visit_spill(V);
@@ -352,32 +348,33 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 flags |= DEG_FLAG_HASH_FULL;
                 break;
             }
-            bool isnew = visit_insert(V, nb, nb >= 0);
-            uint64_t nm = ballot(isnew);
-            int cnt = __popcll(nm);
+            const bool isnew = visit_insert(V, nb, nb >= 0);
+            const uint64_t nm = ballot(isnew);
+            const int cnt = __popcll(nm);
             V.count += cnt;
             evals += cnt;
             f_acc_s = 0.f;
             f_acc_r = 0.f;
             if (cnt == 0) continue;
-            if (isnew) cid[prefix_in(nm)] = nb;
-            wave_sync();
-            const int32_t cand = lane < cnt ? cid[lane] : -1;
-            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, cid, cdist, cnt, nch, mask_tail);
-            const uint64_t ck = lane < cnt ? make_key(cd, cand) : KEY_MAX;
+            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail);
+            const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
+
+            // the closest new candidate is the likely next pop: load its row now
+            spec_v = key_id(wave_min_u64(ck));
+            spec_nb = lane < deg ? P.adj[(int64_t)spec_v * P.astride + lane] : -1;
 
             // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
-            const uint64_t old_first = R[0];
+            const uint64_t old_first = read_lane_u64(R[0], 0);
             int na;
-            bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, lane < cnt && cand != vtx, kst,
-                                     mbuf, t10, na);
+            const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && nb != vtx),
+                                           mbuf, t10, na);
             if (chg) last_chg = hops;
-            if (read_lane_u64(R[0], 0) != read_lane_u64(old_first, 0)) last_d1 = hops;
+            if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
             r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
 
             // S <- S u {n : delta(n,q) <= r (1 + eps)}
             const float thr = thr_of(r, onep);
-            const bool push = lane < cnt && cd <= thr;
+            const bool push = isnew && cd <= thr;
             const uint64_t pm = ballot(push);
             const int np = __popcll(pm);
             f_acc_s = (float)np / (float)deg;
@@ -395,7 +392,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         }
 
         // ---- trace labels: 1 where the top-10 no longer changes afterwards
-        if (P.trace != nullptr) {
+        if (FEAT && P.trace != nullptr) {
             for (int i = lane; i < P.trace_rows; i += WAVE) {
                 float *row = P.trace + ((int64_t)qi * P.trace_rows + i) * TRACE_W;
                 float lab = -1.0f;
@@ -409,17 +406,14 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             uint64_t NK[RREG];
 #pragma unroll
             for (int r2 = 0; r2 < RREG; ++r2) {
-                int base = r2 * WAVE;
-                int cntr = rcnt - base;
+                int cntr = rcnt - r2 * WAVE;
                 cntr = cntr < 0 ? 0 : (cntr > WAVE ? WAVE : cntr);
                 NK[r2] = KEY_MAX;
                 if (cntr > 0) {
-                    int32_t id = lane < cntr ? key_id(R[r2]) : 0;
-                    cid[lane] = id;
-                    wave_sync();
-                    float dd = batch_dist<DT, METRIC, QCH, true>(P, qv, cid, cdist, cntr, nch, mask_tail);
+                    const uint64_t pm2 = cntr == WAVE ? ~0ull : ((1ull << cntr) - 1ull);
+                    const int32_t id = lane < cntr ? key_id(R[r2]) : 0;
+                    float dd = batch_dist<DT, METRIC, QCH, true>(P, qv, id, pm2, nch, mask_tail);
                     NK[r2] = lane < cntr ? make_key(dd, id) : KEY_MAX;
-                    wave_sync();
                 }
             }
 #pragma unroll
@@ -468,31 +462,39 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
 using KernelFn = void (*)(SearchParams);
 
 template <int DT, int METRIC, int QCH>
-static KernelFn pick_r(int rreg) {
+static KernelFn pick_r(int rreg, bool feat) {
+    if (feat) {
+        switch (rreg) {
+            case 1: return search_kernel<DT, METRIC, QCH, 1, true>;
+            case 2: return search_kernel<DT, METRIC, QCH, 2, true>;
+            case 4: return search_kernel<DT, METRIC, QCH, 4, true>;
+            default: return search_kernel<DT, METRIC, QCH, 8, true>;
+        }
+    }
     switch (rreg) {
-        case 1: return search_kernel<DT, METRIC, QCH, 1>;
-        case 2: return search_kernel<DT, METRIC, QCH, 2>;
-        case 4: return search_kernel<DT, METRIC, QCH, 4>;
-        default: return search_kernel<DT, METRIC, QCH, 8>;
+        case 1: return search_kernel<DT, METRIC, QCH, 1, false>;
+        case 2: return search_kernel<DT, METRIC, QCH, 2, false>;
+        case 4: return search_kernel<DT, METRIC, QCH, 4, false>;
+        default: return search_kernel<DT, METRIC, QCH, 8, false>;
     }
 }
 template <int DT, int METRIC>
-static KernelFn pick_q(int qch, int rreg) {
+static KernelFn pick_q(int qch, int rreg, bool feat) {
     switch (qch) {
-        case 1: return pick_r<DT, METRIC, 1>(rreg);
-        case 2: return pick_r<DT, METRIC, 2>(rreg);
-        case 4: return pick_r<DT, METRIC, 4>(rreg);
-        default: return pick_r<DT, METRIC, 12>(rreg);
+        case 1: return pick_r<DT, METRIC, 1>(rreg, feat);
+        case 2: return pick_r<DT, METRIC, 2>(rreg, feat);
+        case 4: return pick_r<DT, METRIC, 4>(rreg, feat);
+        default: return pick_r<DT, METRIC, 12>(rreg, feat);
     }
 }
 template <int DT>
-static KernelFn pick_m(int metric, int qch, int rreg) {
-    return metric == DEG_METRIC_L2 ? pick_q<DT, DEG_METRIC_L2>(qch, rreg)
-                                   : pick_q<DT, DEG_METRIC_IP>(qch, rreg);
+static KernelFn pick_m(int metric, int qch, int rreg, bool feat) {
+    return metric == DEG_METRIC_L2 ? pick_q<DT, DEG_METRIC_L2>(qch, rreg, feat)
+                                   : pick_q<DT, DEG_METRIC_IP>(qch, rreg, feat);
 }
 
-KernelFn pick_kernel_f32(int metric, int qch, int rreg);
-KernelFn pick_kernel_bf16(int metric, int qch, int rreg);
-KernelFn pick_kernel_fp8(int metric, int qch, int rreg);
+KernelFn pick_kernel_f32(int metric, int qch, int rreg, bool feat);
+KernelFn pick_kernel_bf16(int metric, int qch, int rreg, bool feat);
+KernelFn pick_kernel_fp8(int metric, int qch, int rreg, bool feat);
 
 }  // namespace degk

@@ -109,9 +109,12 @@ __device__ __forceinline__ float key_dist(uint64_t k) { return f_of_ord((uint32_
 __device__ __forceinline__ int32_t key_id(uint64_t k) { return (int32_t)(uint32_t)k; }
 
 // ---------------------------------------------------------------- wave helpers
+// Lanes of one wavefront communicate through LDS, which executes a wave's
+// instructions in order; only the compiler must not move LDS accesses across
+// such a point, so wave_sync is a code-motion barrier, not a memory fence.
 __device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
 }
 __device__ __forceinline__ int lane_id() { return (int)threadIdx.x & (WAVE - 1); }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -130,21 +133,48 @@ __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
     uint32_t hi = __shfl_xor((int)(uint32_t)(v >> 32), m);
     return ((uint64_t)hi << 32) | (uint32_t)lo;
 }
+// Rotate within rows of 16 lanes by R (DPP row_ror); lanes keep their own
+// value where the source is masked.
+template <int R>
+__device__ __forceinline__ uint64_t row_ror_u64(uint64_t v) {
+    int lo = __builtin_amdgcn_update_dpp((int)(uint32_t)v, (int)(uint32_t)v, 0x120 + R, 0xF, 0xF, false);
+    int hi = __builtin_amdgcn_update_dpp((int)(uint32_t)(v >> 32), (int)(uint32_t)(v >> 32), 0x120 + R,
+                                         0xF, 0xF, false);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+// Wave minimum / maximum of a 64-bit key (idempotent: rotations within the
+// four rows of 16 lanes, then the four row results through readlane).
 __device__ __forceinline__ uint64_t wave_min_u64(uint64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        uint64_t o = shfl_xor_u64(v, m);
-        v = o < v ? o : v;
-    }
-    return v;
+    uint64_t o;
+    o = row_ror_u64<8>(v); v = o < v ? o : v;
+    o = row_ror_u64<4>(v); v = o < v ? o : v;
+    o = row_ror_u64<2>(v); v = o < v ? o : v;
+    o = row_ror_u64<1>(v); v = o < v ? o : v;
+    uint64_t a = read_lane_u64(v, 0), b = read_lane_u64(v, 16);
+    uint64_t c = read_lane_u64(v, 32), d = read_lane_u64(v, 48);
+    a = b < a ? b : a;
+    c = d < c ? d : c;
+    return c < a ? c : a;
 }
 __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v) {
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) {
-        uint64_t o = shfl_xor_u64(v, m);
-        v = o > v ? o : v;
-    }
-    return v;
+    uint64_t o;
+    o = row_ror_u64<8>(v); v = o > v ? o : v;
+    o = row_ror_u64<4>(v); v = o > v ? o : v;
+    o = row_ror_u64<2>(v); v = o > v ? o : v;
+    o = row_ror_u64<1>(v); v = o > v ? o : v;
+    uint64_t a = read_lane_u64(v, 0), b = read_lane_u64(v, 16);
+    uint64_t c = read_lane_u64(v, 32), d = read_lane_u64(v, 48);
+    a = b > a ? b : a;
+    c = d > c ? d : c;
+    return c > a ? c : a;
+}
+__device__ __forceinline__ int wave_sum_i32(int v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false);  // row_ror:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false);  // row_ror:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false);  // row_ror:1
+    return __builtin_amdgcn_readlane(v, 0) + __builtin_amdgcn_readlane(v, 16) +
+           __builtin_amdgcn_readlane(v, 32) + __builtin_amdgcn_readlane(v, 48);
 }
 __device__ __forceinline__ float thr_of(float r, float onep) {
     // r (1 + eps) of Algorithm 1; infinity stays infinity
@@ -203,36 +233,53 @@ __device__ __forceinline__ float acc_chunk(float acc, float4 x, float4 q) {
     return acc;
 }
 
-// xor butterfly over the 32 lanes of a half-wave; pairs (p, p+w) as the tree does
+// Halving tree over the 32 lanes of a half-wave: step w adds the value of
+// lane p + w to lane p, for w = 16 (swizzle), 8, 4, 2, 1 (DPP row shifts), so
+// lane 0 of each half ends with ((p0 + p16) + (p8 + p24)) + ... exactly as the
+// fixed order prescribes. Only lanes 0 and 32 hold the sum afterwards.
+template <int CTRL>
+__device__ __forceinline__ float dpp_row(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                 0xF, 0xF, true));
+}
 __device__ __forceinline__ float half_reduce(float a) {
-    a = __fadd_rn(a, __shfl_xor(a, 16, 32));
-    a = __fadd_rn(a, __shfl_xor(a, 8, 32));
-    a = __fadd_rn(a, __shfl_xor(a, 4, 32));
-    a = __fadd_rn(a, __shfl_xor(a, 2, 32));
-    a = __fadd_rn(a, __shfl_xor(a, 1, 32));
+    a = __fadd_rn(a, __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, a),
+                                                                           0x401F)));
+    a = __fadd_rn(a, dpp_row<0x108>(a));  // row_shl:8  lane p <- p + 8
+    a = __fadd_rn(a, dpp_row<0x104>(a));  // row_shl:4
+    a = __fadd_rn(a, dpp_row<0x102>(a));  // row_shl:2
+    a = __fadd_rn(a, dpp_row<0x101>(a));  // row_shl:1
     return a;
 }
 
-// Distances of up to 64 candidates; lane j < ncand holds candidate j in `cid`
-// (LDS, already written). Result for candidate j is returned in lane j.
-// Rounds of G candidates per half-wave are loaded before any is reduced so
-// that many row loads are in flight. F32ROWS reads the FP32 rows (rerank)
-// instead of the traversal store.
+// Distances of the candidates in the lanes set in `mask` (each lane holds its
+// id in `cand`); the distance of a candidate is returned in its own lane.
+// Each round takes the next two set lanes: half-wave 0 evaluates the first,
+// half-wave 1 the second. Ids reach the halves and results come back through
+// readlane (no LDS round trip); rounds of G candidates per half are loaded
+// before any is reduced so that many row loads are in flight. F32ROWS reads
+// the FP32 rows (rerank) instead of the traversal store.
 template <int DT, int METRIC, int QCH, bool F32ROWS = false>
 __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
-                                            const int32_t *cid, float *cdist, int ncand,
-                                            int nch, bool mask_tail) {
+                                            int32_t cand, uint64_t mask, int nch, bool mask_tail) {
     constexpr int G = QCH <= 1 ? 8 : (QCH <= 2 ? 4 : (QCH <= 4 ? 2 : 1));
     const int lane = lane_id();
     const int half = lane >> 5, p = lane & 31;
-    const int rounds = (ncand + 1) >> 1;
-    for (int t0 = 0; t0 < rounds; t0 += G) {
+    float res = 0.0f;
+    uint64_t m = mask;
+    while (m) {
         float4 xv[G][QCH];
+        int b0[G], b1[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            int j = 2 * (t0 + g) + half;
-            bool ok = (t0 + g) < rounds && j < ncand;
-            int32_t id = ok ? cid[j] : 0;
+            b0[g] = m ? (int)__builtin_ctzll(m) : -1;
+            if (m) m &= m - 1;
+            b1[g] = m ? (int)__builtin_ctzll(m) : -1;
+            if (m) m &= m - 1;
+            int32_t id0 = b0[g] >= 0 ? __builtin_amdgcn_readlane(cand, b0[g]) : 0;
+            int32_t id1 = b1[g] >= 0 ? __builtin_amdgcn_readlane(cand, b1[g]) : 0;
+            const bool ok = (half ? b1[g] : b0[g]) >= 0;
+            const int32_t id = half ? id1 : id0;
             float sc = 1.0f;
             if constexpr (DT == DT_FP8 && !F32ROWS) {
                 if (ok) sc = P.scale[id];
@@ -255,7 +302,7 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            int j = 2 * (t0 + g) + half;
+            if (b0[g] < 0) break;
             float acc = 0.0f;
 #pragma unroll
             for (int c = 0; c < QCH; ++c) {
@@ -271,11 +318,13 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
             }
             acc = half_reduce(acc);
             if (METRIC == DEG_METRIC_IP) acc = __fsub_rn(1.0f, acc);
-            if (p == 0 && (t0 + g) < rounds && j < ncand) cdist[j] = acc;
+            const float d0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc), 0));
+            const float d1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, acc), 32));
+            if (lane == b0[g]) res = d0;
+            if (lane == b1[g]) res = d1;
         }
     }
-    wave_sync();
-    return lane < ncand ? cdist[lane] : 0.0f;
+    return res;
 }
 
 // ---------------------------------------------------------------- visited set
