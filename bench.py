@@ -31,7 +31,8 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-EPS_SWEEP = [0.0, 0.01, 0.02, 0.05, 0.1, 0.15, 0.2, 0.3, 0.4]
+EPS_SWEEP = [0.0, 0.02, 0.05, 0.08, 0.1, 0.12, 0.15, 0.2, 0.25, 0.3]
+L_SWEEP = [256, 1024]
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "cfg2": dict(desc="1,000,000 x 128 integer Gaussian mixture (1,000 clusters), squared L2, "
@@ -76,7 +77,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--recall", type=float, default=0.95)
-    ap.add_argument("--stop-interval", type=int, default=2)
+    ap.add_argument("--stop-interval", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", default="", help="profile mode: time just this method (P, B or BL)")
@@ -112,31 +113,55 @@ def main(argv=None):
     torch.cuda.synchronize()
     log("device stores ready in %.1fs; seed %d" % (time.time() - t0, seed))
 
-    def run(method, eps, model=None, out=None):
+    # ---- autotune the persistent launch (LDS visited slots, resident waves per CU)
+    from paper_2307_10479_amd import tune
+    tuned = {}
+    ns = min(nq, 4000)
+    for name, store in (("P", s32), ("B", s16)):
+        best, _table = tune.tune(store, G, Q[:ns], seeds[:ns], k, 0.1, save=False)
+        tuned[name] = dict(hash_slots=best["hash_slots"], waves_per_cu=best["waves_per_cu"])
+    log("tuned:", tuned)
+
+    def run(method, eps, model=None, out=None, L=0):
         store = s32 if method == "P" else s16
-        return api.search(store, G, Q, seeds, k, eps, out=out,
+        return api.search(store, G, Q, seeds, k, eps, out=out, queue_cap=L,
                           stop=model if method == "BL" else None)
 
     def sweep(method, model=None):
+        """Recall and time of every (L, eps); the operating point is the fastest
+        setting with recall@10 >= target (capacity L is a speed/recall knob like
+        eps: the oracle with the same L gives the same result)."""
         rows = []
-        for eps in EPS_SWEEP:
-            ids, ds, st = run(method, eps, model)
-            torch.cuda.synchronize()
-            r = metrics.recall_at_k(ids.cpu().numpy(), gt, 10)
-            stn = st.cpu().numpy()
-            rows.append(dict(eps=eps, recall=r, hops=float(stn[:, 0].mean()),
-                             evals=float(stn[:, 1].mean()),
-                             stopped=float(((stn[:, 2] & api.FLAG_LEARNED_STOP) != 0).mean())))
-            if r >= a.recall:
-                break
+        for L in L_SWEEP:
+            for eps in EPS_SWEEP:
+                run(method, eps, model, L=L)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                ids, ds, st = run(method, eps, model, L=L)
+                e1.record()
+                torch.cuda.synchronize()
+                r = metrics.recall_at_k(ids.cpu().numpy(), gt, 10)
+                stn = st.cpu().numpy()
+                rows.append(dict(eps=eps, L=L, recall=r, ms=e0.elapsed_time(e1),
+                                 hops=float(stn[:, 0].mean()), evals=float(stn[:, 1].mean()),
+                                 stopped=float(((stn[:, 2] & api.FLAG_LEARNED_STOP) != 0).mean()),
+                                 overflow=float(((stn[:, 2] & api.FLAG_QUEUE_OVERFLOW) != 0).mean())))
+                if r >= a.recall:
+                    break
         ok = [x for x in rows if x["recall"] >= a.recall]
-        return (ok[0] if ok else rows[-1]), rows
+        best = min(ok, key=lambda x: x["ms"]) if ok else max(rows, key=lambda x: x["recall"])
+        return best, rows
+
+    def fmt(rows):
+        return [(x["L"], x["eps"], round(x["recall"], 4), round(x["ms"], 2), round(x["evals"], 1))
+                for x in rows]
 
     # ---- plain and BF16 operating points
     opP, rowsP = sweep("P")
     opB, rowsB = sweep("B")
-    log("P  sweep:", [(x["eps"], round(x["recall"], 4), round(x["evals"], 1)) for x in rowsP])
-    log("B  sweep:", [(x["eps"], round(x["recall"], 4), round(x["evals"], 1)) for x in rowsB])
+    log("P  sweep (L, eps, recall, ms, evals):", fmt(rowsP))
+    log("B  sweep (L, eps, recall, ms, evals):", fmt(rowsB))
 
     # ---- learned stop: traces, training, calibration (all on the GPU)
     t1 = time.time()
@@ -147,12 +172,16 @@ def main(argv=None):
     tseeds = torch.full((Tq.shape[0], 1), seed, dtype=torch.int32, device="cuda")
     hseeds = torch.full((nhold, 1), seed, dtype=torch.int32, device="cuda")
     train_eps = sorted(set([0.0, opB["eps"], min(0.4, opB["eps"] * 2 + 0.02)]))
-    X, y = stop.collect_traces(s16, G, Tq, tseeds, k, train_eps, interval=a.stop_interval)
+    X, y = stop.collect_traces(s16, G, Tq, tseeds, k, train_eps, interval=a.stop_interval,
+                               rows=512, chunk=25_000, queue_cap=opB["L"])
+    if X.shape[0] > 8_000_000:  # a uniform subsample of the trace rows bounds training time
+        sel = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(1))[:8_000_000].cuda()
+        X, y = X[sel], y[sel]
     mean, inv_std = stop.standardise(X)
     Xs = ((X - mean) * inv_std).contiguous()
     params, hist = stop.train(Xs, y.contiguous(), epochs=4)
     tau, cal = stop.calibrate(s16, G, Hq, hseeds, k, opB["eps"], params, mean, inv_std,
-                              a.stop_interval)
+                              a.stop_interval, queue_cap=opB["L"])
     model = stop.build_model(params, mean, inv_std, tau, a.stop_interval)
     torch.cuda.synchronize()
     log("stop model: %d rows (%.2f positive), loss %s, tau %.3f, calibration %s, %.1fs"
@@ -160,23 +189,22 @@ def main(argv=None):
            [(t, round(g, 4), round(h, 1)) for t, g, h in cal], time.time() - t1))
     del X, y, Xs, Tq
     opBL, rowsBL = sweep("BL", model)
-    log("BL sweep:", [(x["eps"], round(x["recall"], 4), round(x["evals"], 1), round(x["stopped"], 3))
-                      for x in rowsBL])
+    log("BL sweep (L, eps, recall, ms, evals):", fmt(rowsBL))
 
     # ---- timed steps
-    def timed(method, eps, mdl=None):
+    def timed(method, eps, mdl=None, L=0):
         ids = torch.empty((nq, k), dtype=torch.int32, device="cuda")
         ds = torch.empty((nq, k), dtype=torch.float32, device="cuda")
         st = torch.empty((nq, 4), dtype=torch.int32, device="cuda")
         out = (ids, ds, st)
         for _ in range(a.warmup):
-            run(method, eps, mdl, out)
+            run(method, eps, mdl, out, L)
         torch.cuda.synchronize()
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
         for _ in range(a.steps):
-            run(method, eps, mdl, out)
+            run(method, eps, mdl, out, L)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / a.steps
@@ -188,17 +216,17 @@ def main(argv=None):
     for name, op, mdl in (("P", opP, None), ("B", opB, None), ("BL", opBL, model)):
         if a.only and name != a.only:
             continue
-        ms, stn, r = timed(name, op["eps"], mdl)
+        ms, stn, r = timed(name, op["eps"], mdl, op["L"])
         row_bytes = 4 * m if name == "P" else 2 * m
         evals = int(stn[:, 1].astype(np.int64).sum())
         hops = int(stn[:, 0].astype(np.int64).sum())
         rerank = 0 if name == "P" else nq * k * 4 * m
         alg_bytes = evals * row_bytes + hops * 4 * d + nq * (4 * m + 8 * k) + rerank
-        res[name] = dict(eps=op["eps"], recall=r, ms=ms, qps=nq / (ms / 1e3),
+        res[name] = dict(eps=op["eps"], L=op["L"], recall=r, ms=ms, qps=nq / (ms / 1e3),
                          hops=hops / nq, evals=evals / nq, alg_bytes=alg_bytes,
                          gbs=alg_bytes / (ms / 1e3) / 1e9)
-        log("%-2s eps %.3f recall %.4f  %.3f ms/step  %.0f QPS  hops %.1f evals %.1f  %.0f GB/s"
-            % (name, op["eps"], r, ms, res[name]["qps"], hops / nq, evals / nq, res[name]["gbs"]))
+        log("%-2s L %d eps %.3f recall %.4f  %.3f ms/step  %.0f QPS  hops %.1f evals %.1f  %.0f GB/s"
+            % (name, op["L"], op["eps"], r, ms, res[name]["qps"], hops / nq, evals / nq, res[name]["gbs"]))
 
     head = res.get("BL") or next(iter(res.values()))
     # ---- CPU baseline: the oracle's Algorithm 1 on a bounded sample, all host threads
@@ -237,8 +265,8 @@ def main(argv=None):
         "config": {
             "workload": "%s: %s" % (a.workload, WORKLOADS[a.workload]["desc"]),
             "method": "BL: BF16 traversal + FP32 rerank + learned early stop",
-            "k": k, "eps": head["eps"], "recall@10": round(head["recall"], 5),
-            "tau": tau, "stop_interval": a.stop_interval,
+            "k": k, "eps": head["eps"], "queue_cap": head["L"], "recall@10": round(head["recall"], 5),
+            "tau": tau, "stop_interval": a.stop_interval, "tuned": tuned,
             "hops_per_query": round(head["hops"], 2), "evals_per_query": round(head["evals"], 2),
             "plain_fp32": {kk: (round(v, 5) if isinstance(v, float) else v)
                            for kk, v in res.get("P", {}).items()},

@@ -105,7 +105,7 @@ typedef struct {
 
 /* Search options. Zero-initialised means: defaults. */
 typedef struct {
-    int32_t queue_cap;  /* capacity L of the candidate set S; 0 = default max(512, 8 k_pool) */
+    int32_t queue_cap;  /* capacity L of the candidate set S; 0 = default max(256, 8 k_pool) */
     int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = default */
     int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
                            from f32_data when k_pool > k or dtype != DEG_F32; 0 = k */

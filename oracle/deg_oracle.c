@@ -26,8 +26,10 @@
  *     increasing index order, then a halving tree p += p + w for w = 16..1.
  *   - Algorithm 1 starts with the checked set C equal to the seeds (the
  *     printed C = {} would let a seed be checked twice).
- *   - The candidate set S may be bounded by a capacity L (0 = unbounded);
- *     on overflow the largest entry is dropped.
+ *   - The candidate set S may be bounded by a capacity L (0 = unbounded):
+ *     after a hop, if S holds more than L + 64 entries, the dead ones
+ *     (farther than the threshold) are dropped, and if still more than
+ *     L + 64 remain, only the L smallest are kept.
  *   - threshold = fl32(r * fl32(1 + eps)); r = inf gives inf.
  *   - Exploratory (indexed) search: excluded ids enter S and C but never R.
  *
@@ -291,11 +293,50 @@ static uint64_t splitmix64(uint64_t *s) {
     return z ^ (z >> 31);
 }
 
+static int cmp_ent(const void *a, const void *b) {
+    Ent x = *(const Ent *)a, y = *(const Ent *)b;
+    return ent_less(x, y) ? -1 : (ent_less(y, x) ? 1 : 0);
+}
+
+/*
+ * Capacity of S (a reading; the paper's S is unbounded): at the end of a hop,
+ * if S holds more than L + 64 entries, the entries farther than the threshold
+ * are removed (they can never be expanded); if more than L + 64 remain, only
+ * the L smallest are kept. Returns 1 if live entries were dropped.
+ */
+static int apply_capacity(Ctx *c, int64_t L, float thr) {
+    if (c->hsize <= L + 64) return 0;
+    int64_t n = 0;
+    for (int64_t i = 0; i < c->hsize; ++i)
+        if (c->heap[i].d <= thr) c->heap[n++] = c->heap[i];
+    int dropped = 0;
+    if (n > L + 64) {
+        qsort(c->heap, (size_t)n, sizeof(Ent), cmp_ent);
+        n = L;
+        dropped = 1;
+    }
+    c->hsize = n;
+    for (int64_t i = n / 2 - 1; i >= 0; --i) { /* restore the heap: sift down, bottom up */
+        int64_t j = i;
+        for (;;) {
+            int64_t l = 2 * j + 1, rr = l + 1, b = j;
+            if (l < n && ent_less(c->heap[l], c->heap[b])) b = l;
+            if (rr < n && ent_less(c->heap[rr], c->heap[b])) b = rr;
+            if (b == j) break;
+            Ent t = c->heap[j];
+            c->heap[j] = c->heap[b];
+            c->heap[b] = t;
+            j = b;
+        }
+    }
+    return dropped;
+}
+
 /*
  * RangeSearch (Algorithm 1) for one query.
  *   seeds/ns     : seed vertices (distinct)
  *   ex/nex       : ids never placed in R (exploratory search excludes the query vertex)
- *   cap_L        : capacity of S (0 = unbounded); the largest entry is dropped on overflow
+ *   cap_L        : capacity of S (0 = unbounded), applied at the end of each hop
  *   order_mode   : 0 = neighbours in row order, 1 = reversed, 2 = shuffled (seeded);
  *                  the result must not depend on it
  *   want_live    : compute the largest number of live S entries (dist <= threshold)
@@ -331,18 +372,9 @@ static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, con
         heap_push(c, e);
         if (!is_excluded(t, ex, nex)) insert_R(c, &rsize, k, e, &r);
     }
-    if (cap_L > 0) {
-        while (c->hsize > cap_L) {
-            int64_t im = 0;
-            for (int64_t i = 1; i < c->hsize; ++i)
-                if (ent_less(c->heap[im], c->heap[i])) im = i;
-            if (c->heap[im].d <= thr_of(r, onep)) s.overflow = 1;
-            heap_pop_at(c, im);
-        }
-    }
+    if (cap_L > 0 && apply_capacity(c, cap_L, thr_of(r, onep))) s.overflow = 1;
 
     while (c->hsize > 0) {
-        float ev_min = INFINITY; /* smallest distance dropped for capacity in this row */
         Ent sv = heap_pop_at(c, 0); /* argmin of S */
         if (sv.d > thr_of(r, onep)) break; /* too far away: return R */
         s.hops++;
@@ -377,18 +409,10 @@ static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, con
             s.evals++;
             if (dn <= thr_of(r, onep)) { /* close enough to be analysed later */
                 heap_push(c, (Ent){dn, nb});
-                if (cap_L > 0 && c->hsize > cap_L) {
-                    int64_t im = 0;
-                    for (int64_t i = 1; i < c->hsize; ++i)
-                        if (ent_less(c->heap[im], c->heap[i])) im = i;
-                    if (c->heap[im].d < ev_min) ev_min = c->heap[im].d;
-                    heap_pop_at(c, im);
-                }
                 if (dn <= r && !is_excluded(nb, ex, nex)) insert_R(c, &rsize, k, (Ent){dn, nb}, &r);
             }
         }
-        /* a dropped entry matters only if it is still within the end-of-row threshold */
-        if (ev_min <= thr_of(r, onep)) s.overflow = 1;
+        if (cap_L > 0 && apply_capacity(c, cap_L, thr_of(r, onep))) s.overflow = 1;
         if (want_live) {
             int64_t live = 0;
             float t = thr_of(r, onep);

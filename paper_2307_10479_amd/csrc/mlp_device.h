@@ -46,8 +46,8 @@ __device__ __forceinline__ float mlp_logit_bf16(const uint16_t *W, const float (
 #pragma unroll
     for (int i = 0; i < 8; ++i) s = __fmaf_rn(w[i], f[8 + i], s);
     hbuf[j] = fmaxf(s, 0.0f);
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
     s = bf16_val(W[OFF_B2 + j]);
     const float4 *h4 = reinterpret_cast<const float4 *>(hbuf);
 #pragma unroll
@@ -61,10 +61,19 @@ __device__ __forceinline__ float mlp_logit_bf16(const uint16_t *W, const float (
     }
     float h2 = fmaxf(s, 0.0f);
     float z = __fmul_rn(bf16_val(W[OFF_W3 + j]), h2);
-#pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) z = __fadd_rn(z, __shfl_xor(z, m));
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    // sum over the 64 lanes: rotations within rows of 16 (DPP), then the four
+    // row sums through readlane, in a fixed order
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x128, 0xF, 0xF, false)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x124, 0xF, 0xF, false)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x122, 0xF, 0xF, false)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x121, 0xF, 0xF, false)));
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 48));
+    z = __fadd_rn(__fadd_rn(r0, r1), __fadd_rn(r2, r3));
     __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
     return __fadd_rn(z, bf16_val(W[OFF_B3]));
 }
 

@@ -76,9 +76,9 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     int nch = (v->dim + 3) / 4;
     int q = (nch + 31) / 32;
     c.qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
-    int L = (o && o->queue_cap > 0) ? o->queue_cap : (8 * kp > 512 ? 8 * kp : 512);
+    int L = (o && o->queue_cap > 0) ? o->queue_cap : (8 * kp > 256 ? 8 * kp : 256);
     c.L = L;
-    c.scap = ((L > kp ? L : kp) + 63) / 64 * 64;
+    c.scap = ((L + 192 > kp ? L + 192 : kp) + 63) / 64 * 64;  // B (L + 64 + two pushes) / rerank buffer
     const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);
     int H = (o && o->hash_slots) ? o->hash_slots : (t ? t->hash_slots : (kp <= 32 ? 2048 : 4096));
     c.H = H;
@@ -87,7 +87,7 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     while (Hg < 4 * H) Hg <<= 1;
     c.Hg = Hg;
     c.hgshift = 32 - ilog2(Hg);
-    c.lds = 4 * (size_t)H + 8 * (size_t)(c.scap + 64) + 8 * 64 * (size_t)c.rreg + 4 * 64;
+    c.lds = 4 * (size_t)H + 8 * (size_t)c.scap + 8 * 128 + 8 * 64 * (size_t)c.rreg + 4 * 64 + 4 * 64;
     const bool feat = o && (o->stop || o->trace);
     c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg, feat);
     int nb = 0;

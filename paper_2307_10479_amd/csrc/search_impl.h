@@ -11,39 +11,239 @@
 namespace degk {
 
 // ---------------------------------------------------------------- S (candidates)
-// Keeps only keys whose distance is <= thr (the live entries), in order.
-__device__ __forceinline__ int s_prune(uint64_t *Sq, int scnt, float thr) {
+// S is split in two. F, the smallest keys (up to 64), is kept sorted in
+// registers, lane i holding F[i]: a pop reads lane 0 and shifts the wave by one
+// lane. B, all other keys, is an unsorted array in LDS; every key of B is
+// >= beta and every key of F is < beta. New keys below beta are rank-merged
+// into F (the overflow beyond 64 moves to B and lowers beta), the others are
+// appended to B. When F runs empty it is refilled with the 64 smallest live
+// keys of B, found by an exact histogram select. At the end of a hop, if S
+// holds more than L + 64 keys, the dead ones are dropped and, if still more
+// than L + 64 remain, only the L smallest are kept (the capacity reading the
+// oracle applies too).
+struct SQueue {
+    uint64_t f;        // per lane: F[lane], KEY_MAX beyond fcnt
+    int fcnt;          // wave-uniform
+    uint64_t beta;     // wave-uniform
+    uint64_t *B;       // LDS
+    int bcnt;          // wave-uniform
+    uint64_t *stage;   // LDS, 128 keys
+    uint32_t *hist;    // LDS, 64 counters
+};
+
+__device__ __forceinline__ uint64_t lane_shift_down1(uint64_t v) {
+    // lane i <- lane i + 1 (DPP wave_shl:1); lane 63 <- KEY_MAX
+    int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, 0x130, 0xF, 0xF, true);
+    int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), 0x130, 0xF, 0xF, true);
+    uint64_t r = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    return lane_id() == WAVE - 1 ? KEY_MAX : r;
+}
+
+// In-place forward compaction of B keeping keys with distance <= thr.
+__device__ __forceinline__ int b_drop_dead(uint64_t *B, int n, float thr) {
     const int lane = lane_id();
     const uint32_t othr = ord_of(thr);
     int out = 0;
-    for (int base = 0; base < scnt; base += WAVE) {
-        int i = base + lane;
-        uint64_t kk = i < scnt ? Sq[i] : KEY_MAX;
-        bool live = i < scnt && (uint32_t)(kk >> 32) <= othr;
-        uint64_t lm = ballot(live);
+    for (int base = 0; base < n; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < n ? B[i] : KEY_MAX;
+        const bool keep = i < n && (uint32_t)(v >> 32) <= othr;
+        const uint64_t m = ballot(keep);
         wave_sync();
-        if (live) Sq[out + prefix_in(lm)] = kk;
-        out += __popcll(lm);
+        if (keep) B[out + prefix_in(m)] = v;
+        out += __popcll(m);
         wave_sync();
     }
     return out;
 }
 
-// Removes the largest key (the (distance, id) maximum).
-__device__ __forceinline__ void s_evict_max(uint64_t *Sq, int &scnt) {
+// The k-th smallest (1 <= k <= n) of the n distinct keys in B: each round
+// splits the current key range into 64 power-of-two buckets, counts them with
+// LDS atomics and keeps the bucket that holds rank k; at most 64 keys are
+// finally ranked directly.
+__device__ uint64_t b_kth(const uint64_t *B, int n, int k, uint64_t *stage, uint32_t *hist) {
     const int lane = lane_id();
-    uint64_t mx = 0;
-    int mi = -1;
-    for (int i = lane; i < scnt; i += WAVE) {
-        uint64_t kk = Sq[i];
-        if (mi < 0 || kk > mx) { mx = kk; mi = i; }
+    uint64_t mn = KEY_MAX, mx = 0;
+    for (int i = lane; i < n; i += WAVE) {
+        const uint64_t v = B[i];
+        mn = v < mn ? v : mn;
+        mx = v > mx ? v : mx;
     }
-    uint64_t g = wave_max_u64(mi < 0 ? 0 : mx);
-    uint64_t last = Sq[scnt - 1];
+    uint64_t lo = wave_min_u64(mn), hi = wave_max_u64(mx);
+    int kk = k, cnt = n;
+    for (;;) {
+        if (cnt <= WAVE) {
+            int c = 0;
+            for (int base = 0; base < n; base += WAVE) {
+                const int i = base + lane;
+                const uint64_t v = i < n ? B[i] : KEY_MAX;
+                const bool in = i < n && v >= lo && v <= hi;
+                const uint64_t m = ballot(in);
+                if (in) stage[c + prefix_in(m)] = v;
+                c += __popcll(m);
+            }
+            wave_sync();
+            const uint64_t mine = lane < c ? stage[lane] : KEY_MAX;
+            int rank = 0;
+            for (int t = 0; t < c; ++t) rank += stage[t] < mine ? 1 : 0;
+            const uint64_t m = ballot(lane < c && rank == kk - 1);
+            wave_sync();
+            return read_lane_u64(mine, (int)__builtin_ctzll(m));
+        }
+        const uint64_t w0 = (hi - lo) / WAVE + 1;
+        const int sh = w0 <= 1 ? 0 : 64 - __builtin_clzll(w0 - 1);
+        hist[lane] = 0;
+        wave_sync();
+        for (int i = lane; i < n; i += WAVE) {
+            const uint64_t v = B[i];
+            if (v >= lo && v <= hi) atomicAdd(&hist[(uint32_t)((v - lo) >> sh)], 1u);
+        }
+        wave_sync();
+        const int h = (int)hist[lane];
+        int incl = h;
+#pragma unroll
+        for (int d = 1; d < WAVE; d <<= 1) {
+            const int y = __shfl_up(incl, d);
+            if (lane >= d) incl += y;
+        }
+        const uint64_t m = ballot(incl >= kk);
+        const int bk = (int)__builtin_ctzll(m);
+        const int below = __builtin_amdgcn_readlane(incl, bk) - __builtin_amdgcn_readlane(h, bk);
+        cnt = __builtin_amdgcn_readlane(h, bk);
+        kk -= below;
+        lo = lo + ((uint64_t)bk << sh);
+        const uint64_t top = lo + ((1ull << sh) - 1ull);
+        hi = top < hi ? top : hi;
+        wave_sync();
+    }
+}
+
+// Rank-sorts the c <= 64 keys in stage[0..c) into F.
+__device__ __forceinline__ void f_from_stage(SQueue &S, int c) {
+    const int lane = lane_id();
+    const uint64_t mine = lane < c ? S.stage[lane] : KEY_MAX;
+    int rank = 0;
+    for (int t = 0; t < c; ++t) rank += S.stage[t] < mine ? 1 : 0;
     wave_sync();
-    if (mi >= 0 && mx == g) Sq[mi] = last;
-    scnt -= 1;
+    if (lane < c) S.stage[64 + rank] = mine;
     wave_sync();
+    S.f = lane < c ? S.stage[64 + lane] : KEY_MAX;
+    S.fcnt = c;
+    wave_sync();
+}
+
+// F is empty: move the (up to) 64 smallest live keys of B into F.
+__device__ void s_refill(SQueue &S, float thr) {
+    const int lane = lane_id();
+    S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
+    const int n = S.bcnt;
+    if (n == 0) {
+        S.fcnt = 0;
+        S.beta = KEY_MAX;
+        return;
+    }
+    const uint64_t T = n <= WAVE ? KEY_MAX : b_kth(S.B, n, WAVE, S.stage, S.hist);
+    int c = 0, out = 0;
+    for (int base = 0; base < n; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < n ? S.B[i] : KEY_MAX;
+        const bool sel = i < n && v <= T;
+        const bool rest = i < n && v > T;
+        const uint64_t ms = ballot(sel), mr = ballot(rest);
+        wave_sync();
+        if (sel) S.stage[c + prefix_in(ms)] = v;
+        if (rest) S.B[out + prefix_in(mr)] = v;
+        c += __popcll(ms);
+        out += __popcll(mr);
+        wave_sync();
+    }
+    S.bcnt = out;
+    S.beta = out > 0 ? T + 1ull : KEY_MAX;
+    f_from_stage(S, c);
+}
+
+// Pops the smallest key if it lies within thr; false ends the search.
+__device__ __forceinline__ bool s_pop(SQueue &S, float thr, uint64_t &key) {
+    if (S.fcnt == 0) {
+        if (S.bcnt == 0) return false;
+        s_refill(S, thr);
+        if (S.fcnt == 0) return false;
+    }
+    key = read_lane_u64(S.f, 0);
+    if (key_dist(key) > thr) return false;
+    S.f = lane_shift_down1(S.f);
+    S.fcnt -= 1;
+    return true;
+}
+
+// Adds the keys of the lanes in pm.
+__device__ __forceinline__ void s_push(SQueue &S, uint64_t ck, uint64_t pm) {
+    const int lane = lane_id();
+    const uint64_t sm = pm & ballot(ck < S.beta);
+    const uint64_t bg = pm & ~sm;
+    if (bg) {
+        if ((bg >> lane) & 1ull) S.B[S.bcnt + prefix_in(bg)] = ck;
+        S.bcnt += __popcll(bg);
+    }
+    if (sm) {
+        int shift = 0, rank = 0, posF = 0;
+        for (uint64_t m = sm; m; m &= m - 1) {
+            const int t = (int)__builtin_ctzll(m);
+            const uint64_t kt = read_lane_u64(ck, t);
+            shift += kt < S.f ? 1 : 0;
+            rank += kt < ck ? 1 : 0;
+            const int pf = __popcll(ballot(S.f < kt));
+            if (lane == t) posF = pf;
+        }
+        const int tot = S.fcnt + __popcll(sm);
+        if (lane < S.fcnt) S.stage[lane + shift] = S.f;
+        if ((sm >> lane) & 1ull) S.stage[posF + rank] = ck;
+        wave_sync();
+        const int keep = tot < WAVE ? tot : WAVE;
+        S.f = lane < keep ? S.stage[lane] : KEY_MAX;
+        if (tot > WAVE) {
+            const int sp = tot - WAVE;
+            if (lane < sp) S.B[S.bcnt + lane] = S.stage[WAVE + lane];
+            S.beta = read_lane_u64(S.stage[WAVE], 0);
+            S.bcnt += sp;
+        }
+        S.fcnt = keep;
+        wave_sync();
+    }
+}
+
+// End-of-hop capacity rule. Returns true if live keys were dropped.
+__device__ bool s_capacity(SQueue &S, float thr, int L) {
+    const int lane = lane_id();
+    if (S.fcnt + S.bcnt <= L + WAVE) return false;
+    const uint32_t othr = ord_of(thr);
+    const int fl = __popcll(ballot(lane < S.fcnt && (uint32_t)(S.f >> 32) <= othr));
+    S.f = lane < fl ? S.f : KEY_MAX;
+    S.fcnt = fl;
+    S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
+    if (S.fcnt + S.bcnt <= L + WAVE) return false;
+    if (L <= S.fcnt) {
+        S.f = lane < L ? S.f : KEY_MAX;
+        S.fcnt = L;
+        S.bcnt = 0;
+        S.beta = KEY_MAX;
+        return true;
+    }
+    const int keep = L - S.fcnt;
+    const uint64_t T = b_kth(S.B, S.bcnt, keep, S.stage, S.hist);
+    int out = 0;
+    for (int base = 0; base < S.bcnt; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < S.bcnt ? S.B[i] : KEY_MAX;
+        const bool k2 = i < S.bcnt && v <= T;
+        const uint64_t m = ballot(k2);
+        wave_sync();
+        if (k2) S.B[out + prefix_in(m)] = v;
+        out += __popcll(m);
+        wave_sync();
+    }
+    S.bcnt = out;
+    return true;
 }
 
 // ---------------------------------------------------------------- R (results)
@@ -122,9 +322,11 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     const int lane = lane_id();
     const int p = lane & 31;
     int32_t *htab = reinterpret_cast<int32_t *>(smem);
-    uint64_t *Sq = reinterpret_cast<uint64_t *>(smem + 4 * (size_t)P.H);
-    uint64_t *mbuf = Sq + (P.scap + WAVE);
-    float *hbuf = reinterpret_cast<float *>(mbuf + RREG * WAVE);
+    uint64_t *Sq = reinterpret_cast<uint64_t *>(smem + 4 * (size_t)P.H);  // B, P.scap keys
+    uint64_t *stg = Sq + P.scap;                                             // 128 keys
+    uint64_t *mbuf = stg + 2 * WAVE;
+    uint32_t *hist = reinterpret_cast<uint32_t *>(mbuf + RREG * WAVE);
+    float *hbuf = reinterpret_cast<float *>(hist + WAVE);
 
     Visited V;
     V.htab = htab;
@@ -221,7 +423,15 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         int rcnt = 0, total = 0;
         bool ovf = false;
         float r = __builtin_inff();
-        int scnt = 0, hops = 0, evals = 0;
+        SQueue S;
+        S.f = KEY_MAX;
+        S.fcnt = 0;
+        S.beta = KEY_MAX;
+        S.B = Sq;
+        S.bcnt = 0;
+        S.stage = stg;
+        S.hist = hist;
+        int hops = 0, evals = 0;
         const int t10 = kp < 10 ? kp : 10;
         int last_chg = 0, last_d1 = 0;
         float dseed = __builtin_inff(), rprev = __builtin_inff();
@@ -244,40 +454,17 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             int na;
             r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && seed_l != vtx), mbuf, t10, na);
             r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
-            if (isnew) Sq[scnt + prefix_in(nm)] = ck;
-            scnt += cnt;
-            wave_sync();
-            while (scnt > P.L) {
-                s_evict_max(Sq, scnt);
-                flags |= DEG_FLAG_QUEUE_OVERFLOW;
-            }
+            if (cnt > 0) s_push(S, ck, nm);
+            if (s_capacity(S, thr_of(r, onep), P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
         }
 
         // ---- hop loop (Algorithm 1)
-        while (scnt > 0) {
-            // s <- argmin of S; S <- S \ {s}; dead entries (above the threshold) are
-            // dropped when they make up most of S
+        for (;;) {
+            // s <- argmin of S; S <- S \ {s}; stop when S is empty or s is too far away
             const float thr0 = thr_of(r, onep);
-            const uint32_t othr0 = ord_of(thr0);
-            uint64_t mn = KEY_MAX;
-            int mi = -1, live = 0;
-            for (int i = lane; i < scnt; i += WAVE) {
-                uint64_t kk = Sq[i];
-                live += (uint32_t)(kk >> 32) <= othr0 ? 1 : 0;
-                if (kk < mn) { mn = kk; mi = i; }
-            }
-            const uint64_t gmin = wave_min_u64(mn);
+            uint64_t gmin;
+            if (!s_pop(S, thr0, gmin)) break;
             const float ds = key_dist(gmin);
-            if (ds > thr0) break;  // too far away: return R
-            const uint64_t last = Sq[scnt - 1];
-            wave_sync();
-            if (mi >= 0 && mn == gmin) Sq[mi] = last;
-            scnt -= 1;
-            wave_sync();
-            if (scnt > 128) {
-                live = wave_sum_i32(live);
-                if (2 * live < scnt) scnt = s_prune(Sq, scnt, thr0);
-            }
             hops += 1;
 
             // learned stop / trace rows every `interval` hops
@@ -298,7 +485,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 f[6] = logf(1.0f + (float)(hops - last_d1));
                 f[7] = f_acc_s;
                 f[8] = f_acc_r;
-                f[9] = (float)scnt / (float)P.L;
+                f[9] = (float)(S.fcnt + S.bcnt) / (float)P.L;
                 f[10] = __builtin_isinf(thr0) ? 0.f : fminf(ds / fmaxf(thr0, 1e-30f), 4.0f);
                 f[11] = eps;
                 f[12] = logf((float)k);
@@ -379,16 +566,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             const int np = __popcll(pm);
             f_acc_s = (float)np / (float)deg;
             f_acc_r = (float)na / (float)deg;
-            if (np > 0) {
-                if (scnt + np > P.L) scnt = s_prune(Sq, scnt, thr);
-                if (push) Sq[scnt + prefix_in(pm)] = ck;
-                scnt += np;
-                wave_sync();
-                while (scnt > P.L) {
-                    s_evict_max(Sq, scnt);
-                    flags |= DEG_FLAG_QUEUE_OVERFLOW;
-                }
-            }
+            if (np > 0) s_push(S, ck, pm);
+            if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
         }
 
         // ---- trace labels: 1 where the top-10 no longer changes afterwards

@@ -192,23 +192,36 @@ __device__ __forceinline__ float e4m3_value(uint32_t c) {
 }
 
 // ---------------------------------------------------------------- chunk loads
-// Loads chunk `ch` (dims 4ch..4ch+3) of row `id` decoded to FP32.
+// Raw chunk storage per dtype: 16 B of FP32, 8 B of BF16, 4 B of FP8 codes.
+template <int DT> struct RawChunk;
+template <> struct RawChunk<DT_F32> { using T = float4; };
+template <> struct RawChunk<DT_BF16> { using T = uint2; };
+template <> struct RawChunk<DT_FP8> { using T = uint32_t; };
+
+// Loads chunk `ch` (dims 4ch..4ch+3) of row `id` without decoding, so that the
+// wait for the data is not forced right after the load.
 template <int DT>
-__device__ __forceinline__ float4 load_chunk(const SearchParams &P, int32_t id, int ch, float sc) {
+__device__ __forceinline__ typename RawChunk<DT>::T load_raw(const SearchParams &P, int32_t id, int ch) {
     if constexpr (DT == DT_F32) {
-        const float4 *r = reinterpret_cast<const float4 *>(
-            static_cast<const float *>(P.vec) + (int64_t)id * P.vstride);
-        return r[ch];
+        return reinterpret_cast<const float4 *>(static_cast<const float *>(P.vec) +
+                                                (int64_t)id * P.vstride)[ch];
     } else if constexpr (DT == DT_BF16) {
-        const uint2 *r = reinterpret_cast<const uint2 *>(
-            static_cast<const uint16_t *>(P.vec) + (int64_t)id * P.vstride);
-        uint2 u = r[ch];
+        return reinterpret_cast<const uint2 *>(static_cast<const uint16_t *>(P.vec) +
+                                               (int64_t)id * P.vstride)[ch];
+    } else {
+        return reinterpret_cast<const uint32_t *>(static_cast<const uint8_t *>(P.vec) +
+                                                  (int64_t)id * P.vstride)[ch];
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ float4 decode_raw(typename RawChunk<DT>::T u, float sc) {
+    if constexpr (DT == DT_F32) {
+        return u;
+    } else if constexpr (DT == DT_BF16) {
         return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                            __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
     } else {
-        const uint32_t *r = reinterpret_cast<const uint32_t *>(
-            static_cast<const uint8_t *>(P.vec) + (int64_t)id * P.vstride);
-        uint32_t u = r[ch];
         return make_float4(__fmul_rn(sc, e4m3_value(u & 0xffu)),
                            __fmul_rn(sc, e4m3_value((u >> 8) & 0xffu)),
                            __fmul_rn(sc, e4m3_value((u >> 16) & 0xffu)),
@@ -256,47 +269,45 @@ __device__ __forceinline__ float half_reduce(float a) {
 // id in `cand`); the distance of a candidate is returned in its own lane.
 // Each round takes the next two set lanes: half-wave 0 evaluates the first,
 // half-wave 1 the second. Ids reach the halves and results come back through
-// readlane (no LDS round trip); rounds of G candidates per half are loaded
-// before any is reduced so that many row loads are in flight. F32ROWS reads
-// the FP32 rows (rerank) instead of the traversal store.
+// readlane (no LDS round trip). The raw rows of G rounds are loaded first,
+// unconditionally (lanes without work read a valid chunk and are masked to
+// zero afterwards), so that all loads are in flight before any is decoded.
+// F32ROWS reads the FP32 rows (rerank) instead of the traversal store.
 template <int DT, int METRIC, int QCH, bool F32ROWS = false>
 __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
                                             int32_t cand, uint64_t mask, int nch, bool mask_tail) {
     constexpr int G = QCH <= 1 ? 8 : (QCH <= 2 ? 4 : (QCH <= 4 ? 2 : 1));
+    constexpr int DL = F32ROWS ? DT_F32 : DT;
+    using Raw = typename RawChunk<DL>::T;
     const int lane = lane_id();
     const int half = lane >> 5, p = lane & 31;
     float res = 0.0f;
     uint64_t m = mask;
     while (m) {
-        float4 xv[G][QCH];
+        Raw raw[G][QCH];
+        float sc[G];
         int b0[G], b1[G];
+        bool ok[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             b0[g] = m ? (int)__builtin_ctzll(m) : -1;
             if (m) m &= m - 1;
             b1[g] = m ? (int)__builtin_ctzll(m) : -1;
             if (m) m &= m - 1;
-            int32_t id0 = b0[g] >= 0 ? __builtin_amdgcn_readlane(cand, b0[g]) : 0;
-            int32_t id1 = b1[g] >= 0 ? __builtin_amdgcn_readlane(cand, b1[g]) : 0;
-            const bool ok = (half ? b1[g] : b0[g]) >= 0;
-            const int32_t id = half ? id1 : id0;
-            float sc = 1.0f;
-            if constexpr (DT == DT_FP8 && !F32ROWS) {
-                if (ok) sc = P.scale[id];
-            }
+            const int32_t id0 = b0[g] >= 0 ? __builtin_amdgcn_readlane(cand, b0[g]) : 0;
+            const int32_t id1 = b1[g] >= 0 ? __builtin_amdgcn_readlane(cand, b1[g]) : 0;
+            ok[g] = (half ? b1[g] : b0[g]) >= 0;
+            const int32_t id = ok[g] ? (half ? id1 : id0) : 0;
+            sc[g] = 1.0f;
+            if constexpr (DL == DT_FP8) sc[g] = P.scale[id];
 #pragma unroll
             for (int c = 0; c < QCH; ++c) {
-                int ch = p + 32 * c;
-                if (ok && ch < nch) {
-                    if constexpr (F32ROWS) {
-                        const float4 *r =
-                            reinterpret_cast<const float4 *>(P.f32 + (int64_t)id * P.f32_stride);
-                        xv[g][c] = r[ch];
-                    } else {
-                        xv[g][c] = load_chunk<DT>(P, id, ch, sc);
-                    }
+                const int ch = p + 32 * c;
+                const int che = ch < nch ? ch : 0;
+                if constexpr (F32ROWS) {
+                    raw[g][c] = reinterpret_cast<const float4 *>(P.f32 + (int64_t)id * P.f32_stride)[che];
                 } else {
-                    xv[g][c] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    raw[g][c] = load_raw<DL>(P, id, che);
                 }
             }
         }
@@ -306,9 +317,11 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
             float acc = 0.0f;
 #pragma unroll
             for (int c = 0; c < QCH; ++c) {
-                float4 x = xv[g][c];
+                const int ch = p + 32 * c;
+                float4 x = decode_raw<DL>(raw[g][c], sc[g]);
+                if (!ok[g] || ch >= nch) x = make_float4(0.f, 0.f, 0.f, 0.f);
                 if (mask_tail) {
-                    int base = 4 * (p + 32 * c);
+                    const int base = 4 * ch;
                     if (base + 0 >= P.dim) x.x = 0.f;
                     if (base + 1 >= P.dim) x.y = 0.f;
                     if (base + 2 >= P.dim) x.z = 0.f;

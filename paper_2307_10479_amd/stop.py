@@ -23,7 +23,7 @@ from . import api
 
 
 def collect_traces(store, graph, queries, seeds, k, eps_values, interval=2, rows=64,
-                   chunk=50_000):
+                   chunk=50_000, **opts):
     """Runs the plain search with tracing; returns (X, y) on the device (rows with a label)."""
     Xs, ys = [], []
     nq = queries.shape[0]
@@ -35,7 +35,7 @@ def collect_traces(store, graph, queries, seeds, k, eps_values, interval=2, rows
             n = e - s
             trace = torch.empty(n * rows * api.TRACE_W, dtype=torch.float32, device="cuda")
             api.search(store, graph, queries[s:e], seeds[s:e], k, float(eps), trace=trace,
-                       trace_rows=rows, trace_interval=interval)
+                       trace_rows=rows, trace_interval=interval, **opts)
             T = trace.view(n * rows, api.TRACE_W)
             keep = T[:, 16] >= 0
             Xs.append(T[keep, :16].clone())
@@ -101,14 +101,15 @@ def top10_agreement(a_ids, b_ids, k=10):
 
 
 def calibrate(store, graph, queries, seeds, k, eps, params, mean, inv_std, interval,
-              max_loss=0.005, taus=(0.5, 0.6, 0.7, 0.8, 0.85, 0.9, 0.93, 0.95, 0.97, 0.98, 0.99, 0.995)):
+              max_loss=0.005, taus=(0.5, 0.6, 0.7, 0.8, 0.85, 0.9, 0.93, 0.95, 0.97, 0.98, 0.99, 0.995),
+              **opts):
     """Smallest tau whose top-10 agreement with the plain search is >= 1 - max_loss."""
-    plain = api.search(store, graph, queries, seeds, k, eps)
+    plain = api.search(store, graph, queries, seeds, k, eps, **opts)
     best = None
     table = []
     for tau in taus:
         model = build_model(params, mean, inv_std, tau, interval)
-        got = api.search(store, graph, queries, seeds, k, eps, stop=model)
+        got = api.search(store, graph, queries, seeds, k, eps, stop=model, **opts)
         agree = top10_agreement(got[0], plain[0], min(10, k))
         hops = float(got[2][:, 0].float().mean())
         table.append((tau, agree, hops))

@@ -340,3 +340,36 @@ def test_learned_stop_extremes(A):
     stopped = (sa[:, 2] & A.FLAG_LEARNED_STOP) != 0
     assert (sa[stopped, 0] == 3).all()
     assert (sa[~stopped, 0] == sp[~stopped, 0]).all() and (sp[~stopped, 0] < 3).all()
+
+
+def test_hip_graph_capture_replays(A):
+    """The persistent launch (counter reset kernel + search kernel, no memset) can be
+    captured in a HIP graph; every replay, with eager work in between, matches eager."""
+    x, adj = graph(1500, 32, 30, "int")
+    q = synth.small_int(19, 300, 32, hi=256)
+    store = A.VectorStore(dev(x), "bf16")
+    g = A.DeviceGraph(dev(adj))
+    Q = dev(q)
+    seeds = dev(np.zeros((300, 1), np.int32))
+    out = (torch.empty((300, 10), dtype=torch.int32, device="cuda"),
+           torch.empty((300, 10), dtype=torch.float32, device="cuda"),
+           torch.empty((300, 4), dtype=torch.int32, device="cuda"))
+    say("graph capture")
+    ref = [t.cpu().numpy() for t in A.search(store, g, Q, seeds, 10, 0.1)]
+    A.search(store, g, Q, seeds, 10, 0.1, out=out)   # warm the workspace cache
+    torch.cuda.synchronize()
+    cg = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(cg, stream=s):
+            A.search(store, g, Q, seeds, 10, 0.1, out=out)
+    torch.cuda.synchronize()
+    for rep in range(4):
+        for t in out:
+            t.fill_(-7)
+        A.search(store, g, Q[:5], seeds[:5], 3, 0.0)       # unrelated eager work
+        torch.cuda.synchronize()
+        cg.replay()
+        torch.cuda.synchronize()
+        for u, v in zip(out, ref):
+            assert (u.cpu().numpy() == v).all(), rep

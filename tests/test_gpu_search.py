@@ -239,3 +239,35 @@ def test_deterministic(A):
     b = run_gpu(A, x, adj, q, [[0]] * len(q), 10, 0.1)
     for u, v in zip(a, b):
         assert (u == v).all()
+
+
+def test_parity_cfg2_full_size_sampled(A):
+    """1M x 128 workload in the bench's launch configuration (default options, all
+    10,000 queries in one persistent launch); 300 sampled queries checked against
+    the oracle's Algorithm 1 run one by one."""
+    p = DATA / "cfg2.deg"
+    if not p.exists():
+        pytest.skip("data/cfg2.deg not built (python -m oracle.build_graph --cfg 2)")
+    from synth.io import load_graph
+    adj, metric, _ = load_graph(p)
+    base, q = synth.cfg2()
+    say("cfg2 full size")
+    store32 = A.VectorStore(dev(base), "f32")
+    store16 = A.VectorStore(dev(base), "bf16")
+    G = A.DeviceGraph(dev(adj))
+    seed = A.medoid(store32.f32)
+    assert seed == oracle.medoid(base)  # integer data: the GPU medoid equals the oracle's
+    seeds = dev(np.full((q.shape[0], 1), seed, np.int32))
+    sample = synth.rng(70).choice(q.shape[0], size=300, replace=False)
+    for eps, L in ((0.0, 256), (0.1, 256), (0.15, 1024)):
+        say("cfg2 eps", eps, "L", L)
+        ids, ds, st = A.search(store32, G, dev(q), seeds, 10, eps, queue_cap=L)
+        ids16, ds16, st16 = A.search(store16, G, dev(q), seeds, 10, eps, queue_cap=L)
+        torch.cuda.synchronize()
+        ids, ds, st = ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()
+        ref = oracle.range_search(base, adj, q[sample], [seed], 10, eps, cap_L=L)
+        assert_parity((ids[sample], ds[sample], st[sample]), ref, "cfg2 eps=%g L=%d" % (eps, L))
+        ovf = (st[sample, 2] & A.FLAG_QUEUE_OVERFLOW) != 0
+        assert (ovf == (ref[2][:, 3] != 0)).all()
+        # BF16 traversal is lossless on integer data below 256: same result
+        assert (ids16.cpu().numpy() == ids).all() and (ds16.cpu().numpy() == ds).all()
