@@ -183,10 +183,9 @@ __global__ void __launch_bounds__(64) mlp_forward_bf16_kernel(const uint16_t *W,
                                                               int64_t B, float *out) {
     __shared__ __align__(16) float hbuf[64];
     for (int64_t row = blockIdx.x; row < B; row += gridDim.x) {
-        float f[MLP_IN];
-#pragma unroll
-        for (int i = 0; i < MLP_IN; ++i) f[i] = X[row * MLP_IN + i];
-        float z = mlp_logit_bf16(W, f, hbuf);
+        const int lane = (int)threadIdx.x & 63;
+        const float fs = lane < MLP_IN ? X[row * MLP_IN + lane] : 0.0f;
+        float z = mlp_logit_bf16(W, fs, hbuf);
         if (threadIdx.x == 0) out[row] = z;
     }
 }

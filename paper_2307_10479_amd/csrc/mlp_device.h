@@ -19,8 +19,10 @@ constexpr int MLP_NP = OFF_B3 + 1;  // 5313
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // Logit of one feature row with BF16 weights and FP32 accumulation; every
-// lane returns the same value. hbuf: 64 floats of LDS owned by the wave,
-// 16-byte aligned. Weight rows are read as 16-byte vectors (8 BF16 each).
+// lane returns the same value. Lane i < 16 holds standardised feature i in
+// `fs`; the features reach every lane through readlane (no per-lane arrays).
+// hbuf: 64 floats of LDS owned by the wave, 16-byte aligned. Weight rows are
+// read as 16-byte vectors (8 BF16 each).
 __device__ __forceinline__ void bf16x8(const uint4 u, float (&o)[8]) {
     o[0] = __uint_as_float(u.x << 16); o[1] = __uint_as_float(u.x & 0xffff0000u);
     o[2] = __uint_as_float(u.y << 16); o[3] = __uint_as_float(u.y & 0xffff0000u);
@@ -28,38 +30,36 @@ __device__ __forceinline__ void bf16x8(const uint4 u, float (&o)[8]) {
     o[6] = __uint_as_float(u.w << 16); o[7] = __uint_as_float(u.w & 0xffff0000u);
 }
 
-__device__ __forceinline__ float mlp_logit_bf16(const uint16_t *W, const float (&f)[MLP_IN],
-                                                float *hbuf) {
+__device__ __forceinline__ float mlp_logit_bf16(const uint16_t *W, float fs, float *hbuf) {
     const int j = (int)threadIdx.x & 63;
     const uint4 *w1 = reinterpret_cast<const uint4 *>(W + OFF_W1 + j * MLP_IN);
-    const uint4 *w2 = reinterpret_cast<const uint4 *>(W + OFF_W2 + j * MLP_H);
-    uint4 a0 = w1[0], a1 = w1[1];
-    uint4 b[8];
-#pragma unroll
-    for (int t = 0; t < 8; ++t) b[t] = w2[t];
-    float s = bf16_val(W[OFF_B1 + j]);
     float w[8];
-    bf16x8(a0, w);
+    float s = bf16_val(W[OFF_B1 + j]);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s = __fmaf_rn(w[i], f[i], s);
-    bf16x8(a1, w);
+    for (int h = 0; h < 2; ++h) {
+        bf16x8(w1[h], w);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) s = __fmaf_rn(w[i], f[8 + i], s);
+        for (int i = 0; i < 8; ++i) {
+            const float fi = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, fs), 8 * h + i));
+            s = __fmaf_rn(w[i], fi, s);
+        }
+    }
     hbuf[j] = fmaxf(s, 0.0f);
     __builtin_amdgcn_wave_barrier();
     __asm__ volatile("" ::: "memory");
-    s = bf16_val(W[OFF_B2 + j]);
+    const uint4 *w2 = reinterpret_cast<const uint4 *>(W + OFF_W2 + j * MLP_H);
     const float4 *h4 = reinterpret_cast<const float4 *>(hbuf);
+    s = bf16_val(W[OFF_B2 + j]);
 #pragma unroll
     for (int t = 0; t < 8; ++t) {
-        bf16x8(b[t], w);
-        float4 ha = h4[2 * t], hb = h4[2 * t + 1];
+        bf16x8(w2[t], w);
+        const float4 ha = h4[2 * t], hb = h4[2 * t + 1];
         s = __fmaf_rn(w[0], ha.x, s); s = __fmaf_rn(w[1], ha.y, s);
         s = __fmaf_rn(w[2], ha.z, s); s = __fmaf_rn(w[3], ha.w, s);
         s = __fmaf_rn(w[4], hb.x, s); s = __fmaf_rn(w[5], hb.y, s);
         s = __fmaf_rn(w[6], hb.z, s); s = __fmaf_rn(w[7], hb.w, s);
     }
-    float h2 = fmaxf(s, 0.0f);
+    const float h2 = fmaxf(s, 0.0f);
     float z = __fmul_rn(bf16_val(W[OFF_W3 + j]), h2);
     // sum over the 64 lanes: rotations within rows of 16 (DPP), then the four
     // row sums through readlane, in a fixed order

@@ -472,47 +472,45 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             const bool want_trace = FEAT && P.trace != nullptr && (hops % P.trace_interval) == 0 &&
                                     nrow < P.trace_rows;
             if (want_stop || want_trace) {
-                float f[NFEAT];
+                // lane i < 16 computes state feature i (raw); all inputs are wave-uniform
                 const int kq = min(k, rcnt);
                 const float d1 = rcnt > 0 ? key_dist(r_at<RREG>(R, 0)) : 0.f;
-                const float dk = kq > 0 ? key_dist(r_at<RREG>(R, kq - 1)) : 0.f;
-                f[0] = logf(1.0f + (float)hops);
-                f[1] = logf(1.0f + (float)evals);
-                f[2] = (kq > 0 && dk > 0.f) ? d1 / dk : 1.0f;
-                f[3] = (rcnt > 0 && dseed > 0.f && !__builtin_isinf(dseed)) ? d1 / dseed : 1.0f;
-                f[4] = (!__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f) ? r / rprev : 1.0f;
-                f[5] = logf(1.0f + (float)(hops - last_chg));
-                f[6] = logf(1.0f + (float)(hops - last_d1));
-                f[7] = f_acc_s;
-                f[8] = f_acc_r;
-                f[9] = (float)(S.fcnt + S.bcnt) / (float)P.L;
-                f[10] = __builtin_isinf(thr0) ? 0.f : fminf(ds / fmaxf(thr0, 1e-30f), 4.0f);
-                f[11] = eps;
-                f[12] = logf((float)k);
-                f[13] = (float)kind;
-                f[14] = logf(1.0f + (float)V.count);
-                f[15] = 1.0f;
+                const uint64_t kkey = kq > 0 ? r_at<RREG>(R, kq - 1) : KEY_MAX;
+                const float dk = kq > 0 ? key_dist(kkey) : 0.f;
+                // queued candidates (among the 64 smallest) still closer than the k-th result
+                const int closer = __popcll(ballot(lane < S.fcnt && S.f < kkey));
+                float fv;
+                switch (lane) {
+                    case 0: fv = logf(1.0f + (float)hops); break;
+                    case 1: fv = logf(1.0f + (float)evals); break;
+                    case 2: fv = (kq > 0 && dk > 0.f) ? d1 / dk : 1.0f; break;
+                    case 3: fv = (rcnt > 0 && dseed > 0.f && !__builtin_isinf(dseed)) ? d1 / dseed : 1.0f; break;
+                    case 4: fv = (!__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f) ? r / rprev : 1.0f; break;
+                    case 5: fv = logf(1.0f + (float)(hops - last_chg)); break;
+                    case 6: fv = logf(1.0f + (float)(hops - last_d1)); break;
+                    case 7: fv = f_acc_s; break;
+                    case 8: fv = f_acc_r; break;
+                    case 9: fv = (float)closer / 64.0f; break;
+                    case 10: fv = (kq > 0 && dk > 0.f) ? fminf(ds / dk, 4.0f) : 1.0f; break;
+                    case 11: fv = eps; break;
+                    case 12: fv = logf((float)k); break;
+                    case 13: fv = (float)kind; break;
+                    case 14: fv = logf(1.0f + (float)V.count); break;
+                    default: fv = 1.0f; break;
+                }
                 rprev = r;
                 if (want_trace) {
                     float *row = P.trace + ((int64_t)qi * P.trace_rows + nrow) * TRACE_W;
-                    if (lane < NFEAT) {
-                        float fv = 0.f;
-#pragma unroll
-                        for (int i = 0; i < NFEAT; ++i)
-                            if (i == lane) fv = f[i];
-                        row[lane] = fv;
-                    }
+                    if (lane < NFEAT) row[lane] = fv;
                     if (lane == 17) row[17] = (float)qi;
                     if (lane == 18) row[18] = (float)hops;
                     if (lane == 19) row[19] = 0.f;
                     nrow += 1;
                 }
                 if (want_stop) {
-                    float fs[NFEAT];
-#pragma unroll
-                    for (int i = 0; i < NFEAT; ++i)
-                        fs[i] = __fmul_rn(__fsub_rn(f[i], P.stop_mean[i]), P.stop_istd[i]);
-                    float z = mlp_logit_bf16(P.stop_w, fs, hbuf);
+                    const float fs = lane < NFEAT
+                        ? __fmul_rn(__fsub_rn(fv, P.stop_mean[lane]), P.stop_istd[lane]) : 0.0f;
+                    const float z = mlp_logit_bf16(P.stop_w, fs, hbuf);
                     if (z >= P.stop_tau) {
                         flags |= DEG_FLAG_LEARNED_STOP;
                         break;

@@ -2,8 +2,9 @@
 
 1. Traces: the plain search runs with tracing on; every `interval` hops it
    writes its 16 state features (hop and evaluation counts, best/k-th and
-   radius ratios, stagnation counters, acceptance fractions, queue fill,
-   eps, k, exploratory flag, visited count). At the end of a query each row
+   radius ratios, stagnation counters, acceptance fractions, the share of
+   queued candidates closer than the k-th result, the popped distance over
+   the k-th distance, eps, k, exploratory flag, visited count). At the end of a query each row
    is labelled 1 when the top-10 results no longer change afterwards.
 2. Training: the 16-64-64-1 MLP is trained with the library's FP32 forward /
    backward / Adam kernels on standardised features (mean binary
