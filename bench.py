@@ -7,11 +7,13 @@ held-out queries, k = 10, seed = the medoid vertex. The graph, the ground
 truth (exact FP64 kNN) and the medoid come from `python -m oracle.build_graph
 --cfg 2`; the vectors are regenerated from their seeds.
 
-Methods, each at the smallest swept eps whose recall@10 >= target:
+Methods, each at its fastest swept setting whose recall@10 >= target:
   P   plain FP32 traversal (bit-identical to the oracle's Algorithm 1)
   B   BF16 traversal + exact FP32 rerank of the pool
   BL  B + learned early stop (MLP trained here on plain-search traces by the
-      library's own kernels; tau calibrated on held-out training queries)
+      library's own kernels). For each eps from B's operating point upward the
+      stop threshold tau is calibrated on held-out training queries so that
+      the top-10 differs from the plain search at that eps by <= 0.5%.
 A step is one pass of method BL over all queries (one persistent launch).
 The JSON line reports BL's QPS as `value`, P and B alongside, the search
 kernel's achieved algorithmic HBM bandwidth against the 8 TB/s peak, and the
@@ -31,7 +33,8 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-EPS_SWEEP = [0.0, 0.02, 0.05, 0.08, 0.1, 0.12, 0.15, 0.2, 0.25, 0.3]
+EPS_SWEEP = [0.0, 0.05, 0.1, 0.12, 0.14, 0.15, 0.16, 0.17, 0.18, 0.19, 0.2, 0.22, 0.25, 0.3]
+BL_EPS_STEPS = [0.0, 0.02, 0.04, 0.06]  # eps above the B operating point tried with the stop model
 L_SWEEP = [256, 1024]
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
@@ -69,6 +72,37 @@ def load_workload(name):
     return base, q, train, adj, metric, gt, meta
 
 
+def kernel_source_digest() -> str:
+    """SHA-256 over the kernel sources and the C header (the search kernel's inputs)."""
+    import hashlib
+    h = hashlib.sha256()
+    files = sorted((ROOT / "paper_2307_10479_amd" / "csrc").glob("*")) + [ROOT / "include" / "deg.h"]
+    for f in files:
+        if f.suffix in (".h", ".hip"):
+            h.update(f.name.encode())
+            h.update(f.read_bytes())
+    return h.hexdigest()
+
+
+def measured_traffic(workload: str, method: str):
+    """HBM bytes per launch of `method` from the committed counter summary, or None
+    when it is missing or was taken from different kernel sources."""
+    f = ROOT / "profiles" / ("search_kernel_%s_traffic.txt" % workload)
+    if not f.exists():
+        return None
+    kv = {}
+    for line in f.read_text().splitlines():
+        if ":" in line and not line.startswith("#"):
+            key, val = line.split(":", 1)
+            kv[key.strip()] = val.strip()
+    if kv.get("src_sha256") != kernel_source_digest():
+        return None
+    try:
+        return int(kv["%s_fetch_bytes" % method]) + int(kv["%s_write_bytes" % method])
+    except (KeyError, ValueError):
+        return None
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,10 +111,19 @@ def main(argv=None):
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--k", type=int, default=10)
     ap.add_argument("--recall", type=float, default=0.95)
-    ap.add_argument("--stop-interval", type=int, default=4)
+    ap.add_argument("--stop-interval", type=int, default=8)
+    ap.add_argument("--train-eps", default="op", choices=("op", "mix"),
+                    help="trace eps: the operating eps only, or a mix around it")
+    ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", default="", help="profile mode: time just this method (P, B or BL)")
+    ap.add_argument("--only", default="", help="time just these methods (comma list of P, B, BL)")
+    ap.add_argument("--save-state", default="",
+                    help="write the operating points, launch tuning and stop model to this .npz")
+    ap.add_argument("--profile", default="",
+                    help="profile mode: load a --save-state file and run only the timed steps")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="profile mode: first copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
     if a.gpus != 1:
         print("bench.py: this build measures one GPU; the search shards by replicating the index "
@@ -113,19 +156,28 @@ def main(argv=None):
     torch.cuda.synchronize()
     log("device stores ready in %.1fs; seed %d" % (time.time() - t0, seed))
 
-    # ---- autotune the persistent launch (LDS visited slots, resident waves per CU)
-    from paper_2307_10479_amd import tune
     tuned = {}
-    ns = min(nq, 4000)
-    for name, store in (("P", s32), ("B", s16)):
-        best, _table = tune.tune(store, G, Q[:ns], seeds[:ns], k, 0.1, save=False)
-        tuned[name] = dict(hash_slots=best["hash_slots"], waves_per_cu=best["waves_per_cu"])
-    log("tuned:", tuned)
 
     def run(method, eps, model=None, out=None, L=0):
         store = s32 if method == "P" else s16
+        tn = tuned.get("P" if method == "P" else "B", {})
         return api.search(store, G, Q, seeds, k, eps, out=out, queue_cap=L,
-                          stop=model if method == "BL" else None)
+                          stop=model if method == "BL" else None, **tn)
+
+    def measure(method, eps, model, L):
+        run(method, eps, model, L=L)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ids, ds, st = run(method, eps, model, L=L)
+        e1.record()
+        torch.cuda.synchronize()
+        r = metrics.recall_at_k(ids.cpu().numpy(), gt, 10)
+        stn = st.cpu().numpy()
+        return dict(eps=eps, L=L, recall=r, ms=e0.elapsed_time(e1),
+                    hops=float(stn[:, 0].mean()), evals=float(stn[:, 1].mean()),
+                    stopped=float(((stn[:, 2] & api.FLAG_LEARNED_STOP) != 0).mean()),
+                    overflow=float(((stn[:, 2] & api.FLAG_QUEUE_OVERFLOW) != 0).mean()))
 
     def sweep(method, model=None):
         """Recall and time of every (L, eps); the operating point is the fastest
@@ -134,20 +186,8 @@ def main(argv=None):
         rows = []
         for L in L_SWEEP:
             for eps in EPS_SWEEP:
-                run(method, eps, model, L=L)
-                torch.cuda.synchronize()
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record()
-                ids, ds, st = run(method, eps, model, L=L)
-                e1.record()
-                torch.cuda.synchronize()
-                r = metrics.recall_at_k(ids.cpu().numpy(), gt, 10)
-                stn = st.cpu().numpy()
-                rows.append(dict(eps=eps, L=L, recall=r, ms=e0.elapsed_time(e1),
-                                 hops=float(stn[:, 0].mean()), evals=float(stn[:, 1].mean()),
-                                 stopped=float(((stn[:, 2] & api.FLAG_LEARNED_STOP) != 0).mean()),
-                                 overflow=float(((stn[:, 2] & api.FLAG_QUEUE_OVERFLOW) != 0).mean())))
-                if r >= a.recall:
+                rows.append(measure(method, eps, model, L))
+                if rows[-1]["recall"] >= a.recall:
                     break
         ok = [x for x in rows if x["recall"] >= a.recall]
         best = min(ok, key=lambda x: x["ms"]) if ok else max(rows, key=lambda x: x["recall"])
@@ -157,39 +197,88 @@ def main(argv=None):
         return [(x["L"], x["eps"], round(x["recall"], 4), round(x["ms"], 2), round(x["evals"], 1))
                 for x in rows]
 
-    # ---- plain and BF16 operating points
-    opP, rowsP = sweep("P")
-    opB, rowsB = sweep("B")
-    log("P  sweep (L, eps, recall, ms, evals):", fmt(rowsP))
-    log("B  sweep (L, eps, recall, ms, evals):", fmt(rowsB))
+    if a.profile:
+        # ---- profile mode: operating points, tuning and model from an earlier run
+        st = np.load(a.profile)
+        info = json.loads(str(st["info"]))
+        tuned.update(info["tuned"])
+        opP, opB, opBL = info["ops"]["P"], info["ops"]["B"], info["ops"]["BL"]
+        tau = info["tau"]
+        a.stop_interval = info["interval"]
+        model = stop.build_model(dev(st["params"]), dev(st["mean"]), dev(st["inv_std"]), tau,
+                                 a.stop_interval)
+        a.no_cpu_baseline = True
+        if a.copy_mib > 0:
+            cx = torch.empty(a.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
+            cy = torch.empty_like(cx)
+            torch.cuda.synchronize()
+            cy.copy_(cx)
+            torch.cuda.synchronize()
+            log("copy calibration: %d MiB read + %d MiB written by one copy kernel"
+                % (a.copy_mib, a.copy_mib))
+            del cx, cy
+    else:
+        # ---- autotune the persistent launch (LDS visited slots, resident waves per CU)
+        from paper_2307_10479_amd import tune
+        ns = min(nq, 4000)
+        for name, store in (("P", s32), ("B", s16)):
+            best, _table = tune.tune(store, G, Q[:ns], seeds[:ns], k, 0.1, save=False)
+            tuned[name] = dict(hash_slots=best["hash_slots"], waves_per_cu=best["waves_per_cu"])
+        log("tuned:", tuned)
 
-    # ---- learned stop: traces, training, calibration (all on the GPU)
-    t1 = time.time()
-    ntr = train.shape[0]
-    nhold = min(10_000, ntr // 10)
-    Tq = dev(train[: ntr - nhold])
-    Hq = dev(train[ntr - nhold:])
-    tseeds = torch.full((Tq.shape[0], 1), seed, dtype=torch.int32, device="cuda")
-    hseeds = torch.full((nhold, 1), seed, dtype=torch.int32, device="cuda")
-    train_eps = sorted(set([0.0, opB["eps"], min(0.4, opB["eps"] * 2 + 0.02)]))
-    X, y = stop.collect_traces(s16, G, Tq, tseeds, k, train_eps, interval=a.stop_interval,
-                               rows=512, chunk=25_000, queue_cap=opB["L"])
-    if X.shape[0] > 8_000_000:  # a uniform subsample of the trace rows bounds training time
-        sel = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(1))[:8_000_000].cuda()
-        X, y = X[sel], y[sel]
-    mean, inv_std = stop.standardise(X)
-    Xs = ((X - mean) * inv_std).contiguous()
-    params, hist = stop.train(Xs, y.contiguous(), epochs=4)
-    tau, cal = stop.calibrate(s16, G, Hq, hseeds, k, opB["eps"], params, mean, inv_std,
-                              a.stop_interval, queue_cap=opB["L"])
-    model = stop.build_model(params, mean, inv_std, tau, a.stop_interval)
-    torch.cuda.synchronize()
-    log("stop model: %d rows (%.2f positive), loss %s, tau %.3f, calibration %s, %.1fs"
-        % (X.shape[0], float(y.mean()), [round(h, 4) for h in hist], tau,
-           [(t, round(g, 4), round(h, 1)) for t, g, h in cal], time.time() - t1))
-    del X, y, Xs, Tq
-    opBL, rowsBL = sweep("BL", model)
-    log("BL sweep (L, eps, recall, ms, evals):", fmt(rowsBL))
+        # ---- plain and BF16 operating points
+        opP, rowsP = sweep("P")
+        opB, rowsB = sweep("B")
+        log("P  sweep (L, eps, recall, ms, evals):", fmt(rowsP))
+        log("B  sweep (L, eps, recall, ms, evals):", fmt(rowsB))
+
+        # ---- learned stop: traces, training, calibration (all on the GPU)
+        t1 = time.time()
+        ntr = train.shape[0]
+        nhold = min(10_000, ntr // 10)
+        Tq = dev(train[: ntr - nhold])
+        Hq = dev(train[ntr - nhold:])
+        tseeds = torch.full((Tq.shape[0], 1), seed, dtype=torch.int32, device="cuda")
+        hseeds = torch.full((nhold, 1), seed, dtype=torch.int32, device="cuda")
+        bl_eps = [round(opB["eps"] + d, 4) for d in BL_EPS_STEPS]
+        train_eps = (bl_eps if a.train_eps == "op"
+                     else sorted(set([0.0, opB["eps"], min(0.4, opB["eps"] * 2 + 0.02)])))
+        tn = tuned["B"]
+        X, y = stop.collect_traces(s16, G, Tq, tseeds, k, train_eps, interval=a.stop_interval,
+                                   rows=512, chunk=25_000, queue_cap=opB["L"], **tn)
+        if X.shape[0] > 8_000_000:  # a uniform subsample of the trace rows bounds training time
+            sel = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(1))[:8_000_000].cuda()
+            X, y = X[sel], y[sel]
+        mean, inv_std = stop.standardise(X)
+        Xs = ((X - mean) * inv_std).contiguous()
+        params, hist = stop.train(Xs, y.contiguous(), epochs=a.epochs)
+        log("stop model: %d rows (%.2f positive), loss %s, %.1fs"
+            % (X.shape[0], float(y.mean()), [round(h, 4) for h in hist], time.time() - t1))
+        del X, y, Xs, Tq
+        # BL operating point: at each eps from the B operating point upward, tau is
+        # calibrated on held-out training queries (top-10 loss against the plain
+        # search at that eps <= 0.5%); the fastest with recall@10 >= target wins
+        rowsBL = []
+        for eps in bl_eps:
+            tau_e, cal = stop.calibrate(s16, G, Hq, hseeds, k, eps, params, mean, inv_std,
+                                        a.stop_interval, queue_cap=opB["L"], **tn)
+            mdl = stop.build_model(params, mean, inv_std, tau_e, a.stop_interval)
+            row = measure("BL", eps, mdl, opB["L"])
+            row["tau"] = tau_e
+            rowsBL.append(row)
+            log("BL eps %.3f: tau %.3f, calibration %s, recall %.4f, %.2f ms, hops %.1f"
+                % (eps, tau_e, [(t, round(g, 4), round(h, 1)) for t, g, h in cal],
+                   row["recall"], row["ms"], row["hops"]))
+        ok = [x for x in rowsBL if x["recall"] >= a.recall]
+        opBL = min(ok, key=lambda x: x["ms"]) if ok else max(rowsBL, key=lambda x: x["recall"])
+        tau = opBL["tau"]
+        model = stop.build_model(params, mean, inv_std, tau, a.stop_interval)
+        if a.save_state:
+            info = dict(tuned=tuned, ops=dict(P=opP, B=opB, BL=opBL), tau=tau,
+                        interval=a.stop_interval)
+            np.savez(a.save_state, params=params.cpu().numpy(), mean=mean.cpu().numpy(),
+                     inv_std=inv_std.cpu().numpy(), info=json.dumps(info))
+            log("state saved to", a.save_state)
 
     # ---- timed steps
     def timed(method, eps, mdl=None, L=0):
@@ -213,8 +302,9 @@ def main(argv=None):
         return ms, stn, r
 
     res = {}
+    only = [x for x in a.only.split(",") if x]
     for name, op, mdl in (("P", opP, None), ("B", opB, None), ("BL", opBL, model)):
-        if a.only and name != a.only:
+        if only and name not in only:
             continue
         ms, stn, r = timed(name, op["eps"], mdl, op["L"])
         row_bytes = 4 * m if name == "P" else 2 * m
@@ -228,7 +318,8 @@ def main(argv=None):
         log("%-2s L %d eps %.3f recall %.4f  %.3f ms/step  %.0f QPS  hops %.1f evals %.1f  %.0f GB/s"
             % (name, op["L"], op["eps"], r, ms, res[name]["qps"], hops / nq, evals / nq, res[name]["gbs"]))
 
-    head = res.get("BL") or next(iter(res.values()))
+    head_name = "BL" if "BL" in res else next(iter(res))
+    head = res[head_name]
     # ---- CPU baseline: the oracle's Algorithm 1 on a bounded sample, all host threads
     cpu = None
     if not a.no_cpu_baseline:
@@ -276,7 +367,8 @@ def main(argv=None):
         },
         "roofline": {
             "bound": "hbm", "achieved": round(head["gbs"], 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(head["gbs"] / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(head["gbs"] / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(a.workload, head_name),
         },
         "cpu_baseline": cpu,
     }

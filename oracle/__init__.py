@@ -14,6 +14,8 @@ What it covers (each C function cites its passage):
   * the graph checker (Sec. 5.1: even-regular, undirected, loop-free,
     connected, bridgeless)
   * BF16 / FP8-e4m3 encoders and the FP64 MLP forward/backward
+  * BF16 inference of the MLP: BF16 weights, the inputs of both hidden layers
+    rounded to BF16 (nearest-even), wide accumulation
 """
 from __future__ import annotations
 
@@ -364,3 +366,25 @@ def adam_step(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         assert a.dtype == np.float64 and a.flags.c_contiguous
     g = np.ascontiguousarray(grad, np.float64)
     lib().or_adam_step(_p(params), _p(g), _p(m), _p(v), params.shape[0], t, lr, b1, b2, eps)
+
+
+def mlp_logits_bf16(params, X):
+    """BF16 inference of the 16-64-64-1 network (logits, FP64 accumulation).
+
+    `params` are the BF16 weights as values (already representable); the
+    features X and the first hidden layer's ReLU outputs are rounded to BF16
+    (round-to-nearest-even) before they are multiplied; the second hidden
+    layer's outputs enter the final dot product unrounded."""
+    P = np.asarray(params, np.float64)
+    W1 = P[0:1024].reshape(64, 16)
+    b1 = P[1024:1088]
+    W2 = P[1088:5184].reshape(64, 64)
+    b2 = P[5184:5248]
+    w3 = P[5248:5312]
+    b3 = P[5312]
+    xb = bf16_decode(bf16_encode(np.asarray(X, np.float32))).astype(np.float64)
+    h1 = np.maximum(xb @ W1.T + b1, 0.0)
+    h1b = bf16_decode(bf16_encode(h1.astype(np.float32))).astype(np.float64)
+    h2 = np.maximum(h1b @ W2.T + b2, 0.0)
+    return h2 @ w3 + b3
+

@@ -181,11 +181,12 @@ __global__ void mlp_forward_f32(const float *__restrict__ P, const float *__rest
 // One wave per row with the same routine the search uses.
 __global__ void __launch_bounds__(64) mlp_forward_bf16_kernel(const uint16_t *W, const float *X,
                                                               int64_t B, float *out) {
-    __shared__ __align__(16) float hbuf[64];
+    __shared__ __align__(16) uint16_t hbuf[64];
+    const MlpRegs M = mlp_load(W);
     for (int64_t row = blockIdx.x; row < B; row += gridDim.x) {
         const int lane = (int)threadIdx.x & 63;
         const float fs = lane < MLP_IN ? X[row * MLP_IN + lane] : 0.0f;
-        float z = mlp_logit_bf16(W, fs, hbuf);
+        float z = mlp_logit(M, fs, hbuf);
         if (threadIdx.x == 0) out[row] = z;
     }
 }

@@ -326,7 +326,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     uint64_t *stg = Sq + P.scap;                                             // 128 keys
     uint64_t *mbuf = stg + 2 * WAVE;
     uint32_t *hist = reinterpret_cast<uint32_t *>(mbuf + RREG * WAVE);
-    float *hbuf = reinterpret_cast<float *>(hist + WAVE);
+    uint16_t *hbuf = reinterpret_cast<uint16_t *>(hist + WAVE);
 
     Visited V;
     V.htab = htab;
@@ -341,6 +341,17 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     const int deg = P.degree;
     const int hlimit = (3 * P.H) / 4;
     const int glimit = (3 * P.Hg) / 4;
+
+    // stop model: weights and feature standardisation stay in registers for the whole launch
+    MlpRegs M{};
+    float f_mean = 0.f, f_istd = 0.f;
+    if (FEAT && P.stop_w != nullptr) {
+        M = mlp_load(P.stop_w);
+        if (lane < NFEAT) {
+            f_mean = P.stop_mean[lane];
+            f_istd = P.stop_istd[lane];
+        }
+    }
 
     for (;;) {
         int qi = 0;
@@ -435,8 +446,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         const int t10 = kp < 10 ? kp : 10;
         int last_chg = 0, last_d1 = 0;
         float dseed = __builtin_inff(), rprev = __builtin_inff();
-        float f_acc_s = 0.f, f_acc_r = 0.f;
+        int n_acc_s = 0, n_acc_r = 0;
         int nrow = 0;
+        int to_stop = P.stop_interval, to_trace = P.trace_interval;  // hops until the next checkpoint
         int32_t spec_v = -1, spec_nb = -1;  // adjacency row loaded ahead for the likely next pop
 
         // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
@@ -468,9 +480,15 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             hops += 1;
 
             // learned stop / trace rows every `interval` hops
-            const bool want_stop = FEAT && P.stop_w != nullptr && (hops % P.stop_interval) == 0;
-            const bool want_trace = FEAT && P.trace != nullptr && (hops % P.trace_interval) == 0 &&
-                                    nrow < P.trace_rows;
+            bool want_stop = false, want_trace = false;
+            if (FEAT) {
+                to_stop -= 1;
+                to_trace -= 1;
+                want_stop = P.stop_w != nullptr && to_stop == 0;
+                want_trace = P.trace != nullptr && to_trace == 0 && nrow < P.trace_rows;
+                if (to_stop == 0) to_stop = P.stop_interval;
+                if (to_trace == 0) to_trace = P.trace_interval;
+            }
             if (want_stop || want_trace) {
                 // lane i < 16 computes state feature i (raw); all inputs are wave-uniform
                 const int kq = min(k, rcnt);
@@ -479,25 +497,48 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 const float dk = kq > 0 ? key_dist(kkey) : 0.f;
                 // queued candidates (among the 64 smallest) still closer than the k-th result
                 const int closer = __popcll(ballot(lane < S.fcnt && S.f < kkey));
-                float fv;
-                switch (lane) {
-                    case 0: fv = logf(1.0f + (float)hops); break;
-                    case 1: fv = logf(1.0f + (float)evals); break;
-                    case 2: fv = (kq > 0 && dk > 0.f) ? d1 / dk : 1.0f; break;
-                    case 3: fv = (rcnt > 0 && dseed > 0.f && !__builtin_isinf(dseed)) ? d1 / dseed : 1.0f; break;
-                    case 4: fv = (!__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f) ? r / rprev : 1.0f; break;
-                    case 5: fv = logf(1.0f + (float)(hops - last_chg)); break;
-                    case 6: fv = logf(1.0f + (float)(hops - last_d1)); break;
-                    case 7: fv = f_acc_s; break;
-                    case 8: fv = f_acc_r; break;
-                    case 9: fv = (float)closer / 64.0f; break;
-                    case 10: fv = (kq > 0 && dk > 0.f) ? fminf(ds / dk, 4.0f) : 1.0f; break;
-                    case 11: fv = eps; break;
-                    case 12: fv = logf((float)k); break;
-                    case 13: fv = (float)kind; break;
-                    case 14: fv = logf(1.0f + (float)V.count); break;
-                    default: fv = 1.0f; break;
-                }
+                // lane i < 16 gets feature i's value a and divisor b (selected from the
+                // wave-uniform state), then every lane combines them in the same few steps
+                const bool fin_r = !__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f;
+                const bool fin_s = rcnt > 0 && dseed > 0.f && !__builtin_isinf(dseed);
+                const bool fin_k = kq > 0 && dk > 0.f;
+                int ai = __float_as_int(1.0f);
+                ai = lane == 0 ? hops : ai;
+                ai = lane == 1 ? evals : ai;
+                ai = lane == 2 ? __float_as_int(d1) : ai;
+                ai = lane == 3 ? __float_as_int(d1) : ai;
+                ai = lane == 4 ? __float_as_int(r) : ai;
+                ai = lane == 5 ? hops - last_chg : ai;
+                ai = lane == 6 ? hops - last_d1 : ai;
+                ai = lane == 7 ? n_acc_s : ai;
+                ai = lane == 8 ? n_acc_r : ai;
+                ai = lane == 9 ? closer : ai;
+                ai = lane == 10 ? __float_as_int(ds) : ai;
+                ai = lane == 11 ? __float_as_int(eps) : ai;
+                ai = lane == 12 ? k - 1 : ai;
+                ai = lane == 13 ? kind : ai;
+                ai = lane == 14 ? V.count : ai;
+                int bi = __float_as_int(1.0f);
+                bi = lane == 2 ? __float_as_int(dk) : bi;
+                bi = lane == 3 ? __float_as_int(dseed) : bi;
+                bi = lane == 4 ? __float_as_int(rprev) : bi;
+                bi = lane == 7 ? __float_as_int((float)deg) : bi;
+                bi = lane == 8 ? __float_as_int((float)deg) : bi;
+                bi = lane == 9 ? __float_as_int(64.0f) : bi;
+                bi = lane == 10 ? __float_as_int(dk) : bi;
+                const uint32_t okm = (fin_k ? 0x404u : 0u) | (fin_s ? 0x8u : 0u) | (fin_r ? 0x10u : 0u) | 0x380u;
+                const uint32_t lb = 1u << (lane & 31);
+                const bool lane_lo = lane < 16;
+                const bool is_int = lane_lo && (0x73E3u & lb) != 0;    // 0,1,5,6,7,8,9,12,13,14
+                const bool is_log = lane_lo && (0x5063u & lb) != 0;    // 0,1,5,6,12,14
+                const bool is_ratio = lane_lo && (0x079Cu & lb) != 0;  // 2,3,4,7,8,9,10
+                const bool ok = (okm & lb) != 0;
+                const float fa = is_int ? (float)ai : __int_as_float(ai);
+                const float fb = __int_as_float(bi);
+                float fv = fa;
+                if (is_log) fv = 0.69314718f * __log2f(1.0f + fa);
+                if (is_ratio) fv = ok ? fa * __builtin_amdgcn_rcpf(fb) : 1.0f;
+                if (lane == 10) fv = fminf(fv, 4.0f);
                 rprev = r;
                 if (want_trace) {
                     float *row = P.trace + ((int64_t)qi * P.trace_rows + nrow) * TRACE_W;
@@ -508,9 +549,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                     nrow += 1;
                 }
                 if (want_stop) {
-                    const float fs = lane < NFEAT
-                        ? __fmul_rn(__fsub_rn(fv, P.stop_mean[lane]), P.stop_istd[lane]) : 0.0f;
-                    const float z = mlp_logit_bf16(P.stop_w, fs, hbuf);
+                    const float fs = lane < NFEAT ? __fmul_rn(__fsub_rn(fv, f_mean), f_istd) : 0.0f;
+                    const float z = mlp_logit(M, fs, hbuf);
                     if (z >= P.stop_tau) {
                         flags |= DEG_FLAG_LEARNED_STOP;
                         break;
@@ -538,8 +578,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             const int cnt = __popcll(nm);
             V.count += cnt;
             evals += cnt;
-            f_acc_s = 0.f;
-            f_acc_r = 0.f;
+            n_acc_s = 0;
+            n_acc_r = 0;
             if (cnt == 0) continue;
             const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail);
             const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
@@ -562,8 +602,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             const bool push = isnew && cd <= thr;
             const uint64_t pm = ballot(push);
             const int np = __popcll(pm);
-            f_acc_s = (float)np / (float)deg;
-            f_acc_r = (float)na / (float)deg;
+            n_acc_s = np;
+            n_acc_r = na;
             if (np > 0) s_push(S, ck, pm);
             if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
         }

@@ -341,11 +341,14 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
 }
 
 // ---------------------------------------------------------------- visited set
+// Visited set C of one query. It starts in an LDS hash table; when that
+// fills, every id moves to the query's table in the workspace, which from
+// then on is the set.
 struct Visited {
     int32_t *htab;  // LDS
     int32_t *gtab;  // workspace
     int H, hshift, Hg, hgshift;
-    int count;      // wave-uniform
+    int count;      // |C| (wave-uniform)
     bool spilled;   // wave-uniform
 };
 
@@ -353,51 +356,126 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t id, int shift) {
     return ((uint32_t)id * 0x9E3779B1u) >> shift;
 }
 
-// Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the set.
-__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
-    bool isnew = false;
-    if (act) {
-        if (!V.spilled) {
-            uint32_t msk = (uint32_t)V.H - 1u;
-            uint32_t s = hash_slot(id, V.hshift);
-            for (;;) {
-                int32_t old = atomicCAS(&V.htab[s], -1, id);
-                if (old == -1) { isnew = true; break; }
-                if (old == id) break;
-                s = (s + 1u) & msk;
+// Linear-probing insert of `id` into `tab` (power-of-two size msk + 1, a
+// multiple of 4) starting at slot s. Slots are read four at a time (one
+// 16-byte load covers the next probe positions of the aligned group); an
+// empty slot is claimed with compare-and-swap, so a slot only ever goes from
+// -1 to an id. The probe order is the plain linear order s, s+1, ..., so the
+// set is the same as with one-slot probing. A stale read can only show -1
+// where an id already is: the CAS then returns that id and the probe moves on.
+// Returns true where id was not in the set.
+__device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
+    bool isnew = false, done = false;
+    while (!done) {
+        const uint32_t g = s & ~3u;
+        const int4 q4 = *reinterpret_cast<const int4 *>(tab + g);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!done && g + (uint32_t)j >= s) {
+                const int32_t v = j == 0 ? q4.x : (j == 1 ? q4.y : (j == 2 ? q4.z : q4.w));
+                if (v == id) {
+                    done = true;
+                } else if (v == -1) {
+                    const int32_t old = atomicCAS(&tab[g + j], -1, id);
+                    if (old == -1) {
+                        isnew = true;
+                        done = true;
+                    } else if (old == id) {
+                        done = true;
+                    }
+                }
             }
-        } else {
-            uint32_t msk = (uint32_t)V.Hg - 1u;
-            uint32_t s = hash_slot(id, V.hgshift);
-            for (;;) {
-                int32_t old = atomicCAS(&V.gtab[s], -1, id);
-                if (old == -1) { isnew = true; break; }
-                if (old == id) break;
-                s = (s + 1u) & msk;
+        }
+        s = (g + 4u) & msk;
+    }
+    return isnew;
+}
+
+// Linear-probing insert by compare-and-swap on each probed slot (one round
+// trip per probe; suited to a sparsely filled table in global memory).
+__device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
+    for (;;) {
+        const int32_t old = atomicCAS(&tab[s], -1, id);
+        if (old == -1) return true;
+        if (old == id) return false;
+        s = (s + 1u) & msk;
+    }
+}
+
+// Insert into the query's workspace table, which only this wave touches. Each
+// lane reads its next group of four slots and stops at its id (present) or at
+// the first empty slot (new); lanes aiming at the same empty slot are told
+// apart in registers (the lowest lane takes it, the others probe on), and the
+// winners claim their slots with plain stores: one memory round trip for the
+// usual hop, none waiting for a store. The workgroup-scope fence at the top
+// of each round waits for this wave's earlier stores, after which every lane
+// of the wave reads them.
+__device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
+                                              bool act) {
+    const int lane = lane_id();
+    bool isnew = false, pending = act;
+    while (ballot(pending) != 0) {
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        uint32_t target = 0xFFFFFFFFu;
+        if (pending) {
+            const uint32_t g = s & ~3u;
+            const int4 q4 = *reinterpret_cast<const int4 *>(tab + g);
+            bool done = false;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!done && g + (uint32_t)j >= s) {
+                    const int32_t v = j == 0 ? q4.x : (j == 1 ? q4.y : (j == 2 ? q4.z : q4.w));
+                    if (v == id) {
+                        done = true;
+                        pending = false;
+                    } else if (v == -1) {
+                        done = true;
+                        target = g + (uint32_t)j;
+                    }
+                }
             }
+            if (!done) s = (g + 4u) & msk;
+        }
+        // claims: lowest lane per slot wins
+        const uint64_t cm = ballot(target != 0xFFFFFFFFu);
+        bool win = target != 0xFFFFFFFFu;
+        for (uint64_t m = cm; m; m &= m - 1) {
+            const int c = (int)__builtin_ctzll(m);
+            const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)target, c);
+            if (lane > c && tc == target) win = false;
+        }
+        if (win) {
+            tab[target] = id;
+            isnew = true;
+            pending = false;
+        } else if (target != 0xFFFFFFFFu) {
+            s = (target + 1u) & msk;  // the slot is taken by a lower lane: probe on
         }
     }
     return isnew;
 }
 
+// Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the set.
+__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
+    if (!V.spilled) {
+        bool isnew = false;
+        if (act) isnew = probe_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), id);
+        return isnew;
+    }
+    return global_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id, act);
+}
+
 // Moves the LDS table to the workspace table (cleared first).
 __device__ __forceinline__ void visit_spill(Visited &V) {
     const int lane = lane_id();
-    for (int i = lane; i < V.Hg; i += WAVE) V.gtab[i] = -1;
+    int4 *g4 = reinterpret_cast<int4 *>(V.gtab);
+    for (int i = lane; i < (V.Hg >> 2); i += WAVE) g4[i] = make_int4(-1, -1, -1, -1);
     __threadfence();
     wave_sync();
     V.spilled = true;
     for (int i = lane; i < V.H; i += WAVE) {
-        int32_t id = V.htab[i];
-        if (id >= 0) {
-            uint32_t msk = (uint32_t)V.Hg - 1u;
-            uint32_t s = hash_slot(id, V.hgshift);
-            for (;;) {
-                int32_t old = atomicCAS(&V.gtab[s], -1, id);
-                if (old == -1 || old == id) break;
-                s = (s + 1u) & msk;
-            }
-        }
+        const int32_t id = V.htab[i];
+        if (id >= 0) cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id);
     }
     __threadfence();
     wave_sync();

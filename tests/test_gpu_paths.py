@@ -241,8 +241,13 @@ def test_mlp_bf16_forward(A):
     wb = w.cpu().numpy()
     assert (wb == oracle.bf16_encode(P.astype(np.float32))).all()
     Pb = oracle.bf16_decode(wb).astype(np.float64)
-    _, _, rz = oracle.mlp_fwd_bwd(Pb, X)
-    assert np.allclose(z.cpu().numpy(), rz, rtol=1e-4, atol=1e-4)
+    rz = oracle.mlp_logits_bf16(Pb, X)
+    err = np.abs(z.cpu().numpy().astype(np.float64) - rz) / (1.0 + np.abs(rz))
+    # FP32 against FP64 accumulation: ~1e-6. A hidden value within that of a
+    # BF16 rounding midpoint may round the other way on one side (one BF16
+    # step of one unit, a few 1e-3 at most); such rows are rare.
+    assert err.max() <= 1e-2
+    assert (err <= 1e-4).mean() >= 0.98
 
 
 # ---------------------------------------------------------------- batch

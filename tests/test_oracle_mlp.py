@@ -1,5 +1,6 @@
 """Pins of the oracle's MLP (16-64-64-1, ReLU, sigmoid, mean BCE) by central
-finite differences and of its Adam step by the update written out."""
+finite differences, of its Adam step by the update written out, and of its
+BF16 inference by cases where BF16 rounding is exact or known by hand."""
 import numpy as np
 
 import oracle
@@ -51,3 +52,41 @@ def test_adam_step():
     # first step: m = (1-b1) g, v = (1-b2) g^2, bias corrected -> g / (|g| + eps')
     expect = P - 0.01 * g / (np.abs(g) + 1e-8)
     assert np.allclose(p1, expect, rtol=1e-9, atol=1e-12)
+
+
+
+
+def test_bf16_inference_equals_plain_when_every_value_is_bf16_exact():
+    # small integers everywhere: inputs and first-layer outputs are integers
+    # below 256, which BF16 holds exactly, so rounding changes nothing
+    r = synth.rng(7)
+    P = np.zeros(oracle.mlp_nparams())
+    P[0:1024] = r.integers(-2, 3, 1024)
+    P[1024:1088] = r.integers(0, 4, 64)
+    P[1088:5184] = r.integers(-1, 2, 4096)
+    P[5184:5248] = r.integers(0, 3, 64)
+    P[5248:5312] = r.integers(-2, 3, 64)
+    P[5312] = 1.0
+    X = r.integers(0, 4, (50, 16)).astype(np.float32)
+    _, _, plain = oracle.mlp_fwd_bwd(P, X)
+    assert np.abs(P[0:1024]).sum(axis=None) > 0 and np.abs(plain).max() > 0
+    assert (oracle.mlp_logits_bf16(P, X) == plain).all()
+
+
+def test_bf16_inference_rounds_hidden_values_to_nearest_even():
+    # one path: x0 + x1 -> h1[0] -> h2[0] -> z; 128 and 129 are exact in BF16,
+    # their sum 257 is not: it lies halfway between 256 and 258 and rounds to
+    # the even significand (256); 259 lies halfway between 258 and 260 -> 260
+    P = np.zeros(oracle.mlp_nparams())
+    P[0] = 1.0          # W1[0][0]
+    P[1] = 1.0          # W1[0][1]
+    P[1088] = 1.0       # W2[0][0]
+    P[5248] = 1.0       # w3[0]
+    X = np.zeros((3, 16), np.float32)
+    X[0, :2] = (128, 129)
+    X[1, :2] = (128, 131)
+    X[2, :2] = (257, 0)  # the input itself is rounded first: 257 -> 256
+    z = oracle.mlp_logits_bf16(P, X)
+    assert z.tolist() == [256.0, 260.0, 256.0]
+    _, _, plain = oracle.mlp_fwd_bwd(P, X)
+    assert plain.tolist() == [257.0, 259.0, 257.0]
