@@ -436,15 +436,22 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
             }
             if (!done) s = (g + 4u) & msk;
         }
-        // claims: lowest lane per slot wins
+        // claims: lowest lane per slot wins; a loser holding the winner's id
+        // (the same id twice in one adjacency row) finds it present
         const uint64_t cm = ballot(target != 0xFFFFFFFFu);
-        bool win = target != 0xFFFFFFFFu;
+        bool win = target != 0xFFFFFFFFu, dup = false;
         for (uint64_t m = cm; m; m &= m - 1) {
             const int c = (int)__builtin_ctzll(m);
             const uint32_t tc = (uint32_t)__builtin_amdgcn_readlane((int)target, c);
-            if (lane > c && tc == target) win = false;
+            const int32_t ic = __builtin_amdgcn_readlane(id, c);
+            if (lane > c && tc == target) {
+                if (win && ic == id) dup = true;
+                win = false;
+            }
         }
-        if (win) {
+        if (dup) {
+            pending = false;
+        } else if (win) {
             tab[target] = id;
             isnew = true;
             pending = false;

@@ -180,6 +180,25 @@ def test_parity_hash_spill(A):
     assert ((got[2][:, 2] & A.FLAG_HASH_SPILL) != 0).any()
 
 
+@pytest.mark.parametrize("n", [1 << 18, (1 << 19) + 3])
+def test_parity_large_ids_small_table(A, n):
+    """Large ids with a 256-slot LDS table, so every query moves its visited set
+    to the workspace table early; a random adjacency (not a DEG) with one id
+    repeated in every row, which both tables must report as present the second
+    time."""
+    r = synth.rng(70)
+    m, d = 16, 16
+    x = synth.small_int(71, n, m, hi=64)
+    adj = r.integers(0, n, size=(n, d)).astype(np.int32)
+    adj[:, 5] = adj[:, 3]
+    q = queries_for("int", 72, 64, m)
+    say("large ids", n)
+    got = run_gpu(A, x, adj, q, [[0]] * len(q), 20, 0.02, hash_slots=256)
+    ref = oracle.range_search(x, adj, q, [0], 20, 0.02, cap_L=BIG_L)
+    assert_parity(got, ref, "n=%d" % n)
+    assert ((got[2][:, 2] & A.FLAG_HASH_SPILL) != 0).any()
+
+
 def test_parity_indexed(A):
     x, adj = graph(1500, 100, 30, "unit", oracle.IP)
     qids = synth.rng(61).choice(1500, size=200, replace=False).astype(np.int32)
