@@ -183,13 +183,10 @@ __device__ __forceinline__ float thr_of(float r, float onep) {
 }
 
 // ---------------------------------------------------------------- FP8 E4M3 decode
-// Exact value of an OCP E4M3 code: exponent field 0 -> m * 2^-9, else
-// (8 + m) * 2^(e - 10). Code 0x7f/0xff (NaN) never occurs in an encoded store.
-__device__ __forceinline__ float e4m3_value(uint32_t c) {
-    uint32_t e = (c >> 3) & 15u, m = c & 7u;
-    float v = e == 0 ? (float)m * 0.001953125f : __builtin_ldexpf((float)(8u + m), (int)e - 10);
-    return (c & 0x80u) ? -v : v;
-}
+// Value of an OCP E4M3 code: exponent field 0 -> m * 2^-9, else
+// (8 + m) * 2^(e - 10); every such value is exact in FP32. Code 0x7f/0xff
+// (NaN) never occurs in an encoded store.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // ---------------------------------------------------------------- chunk loads
 // Raw chunk storage per dtype: 16 B of FP32, 8 B of BF16, 4 B of FP8 codes.
@@ -222,10 +219,11 @@ __device__ __forceinline__ float4 decode_raw(typename RawChunk<DT>::T u, float s
         return make_float4(__uint_as_float(u.x << 16), __uint_as_float(u.x & 0xffff0000u),
                            __uint_as_float(u.y << 16), __uint_as_float(u.y & 0xffff0000u));
     } else {
-        return make_float4(__fmul_rn(sc, e4m3_value(u & 0xffu)),
-                           __fmul_rn(sc, e4m3_value((u >> 8) & 0xffu)),
-                           __fmul_rn(sc, e4m3_value((u >> 16) & 0xffu)),
-                           __fmul_rn(sc, e4m3_value(u >> 24)));
+        // gfx950 converts OCP E4M3 in hardware (two codes per instruction, exact)
+        const f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, false);
+        const f32x2 hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)u, true);
+        return make_float4(__fmul_rn(sc, lo.x), __fmul_rn(sc, lo.y), __fmul_rn(sc, hi.x),
+                           __fmul_rn(sc, hi.y));
     }
 }
 
@@ -276,8 +274,14 @@ __device__ __forceinline__ float half_reduce(float a) {
 template <int DT, int METRIC, int QCH, bool F32ROWS = false>
 __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
                                             int32_t cand, uint64_t mask, int nch, bool mask_tail) {
-    constexpr int G = QCH <= 1 ? 8 : (QCH <= 2 ? 4 : (QCH <= 4 ? 2 : 1));
     constexpr int DL = F32ROWS ? DT_F32 : DT;
+    // rows in flight per half-wave: a register budget for the raw chunks, so
+    // that narrower storage keeps more rows (and memory requests) in flight
+    constexpr int WPC = DL == DT_F32 ? 4 : (DL == DT_BF16 ? 2 : 1);  // 32-bit words per chunk
+    constexpr int BUDGET = QCH >= 12 ? 96 : 32;
+    constexpr int G0 = BUDGET / (QCH * WPC);
+    constexpr int GMAX = QCH >= 12 ? 4 : 8;
+    constexpr int G = G0 < 1 ? 1 : (G0 > GMAX ? GMAX : G0);
     using Raw = typename RawChunk<DL>::T;
     const int lane = lane_id();
     const int half = lane >> 5, p = lane & 31;
