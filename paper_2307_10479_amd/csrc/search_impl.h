@@ -449,7 +449,10 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         int n_acc_s = 0, n_acc_r = 0;
         int nrow = 0;
         int to_stop = P.stop_interval, to_trace = P.trace_interval;  // hops until the next checkpoint
-        int32_t spec_v = -1, spec_nb = -1;  // adjacency row loaded ahead for the likely next pop
+        // adjacency rows requested ahead for the likely next pop: the runner-up in
+        // S at the previous pop (the next pop in about nine hops of ten) and the
+        // closest new candidate of the previous hop
+        int32_t run_v = -1, run_nb = -1, spec_v = -1, spec_nb = -1;
 
         // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
         if (!bad_query) {
@@ -561,7 +564,10 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             // N <- N(G,s) \ C ; C <- C u N
             const int32_t s = key_id(gmin);
             int32_t nb = -1;
-            if (lane < deg) nb = (s == spec_v) ? spec_nb : P.adj[(int64_t)s * P.astride + lane];
+            if (lane < deg)
+                nb = s == run_v ? run_nb : (s == spec_v ? spec_nb : P.adj[(int64_t)s * P.astride + lane]);
+            run_v = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
+            run_nb = (run_v >= 0 && lane < deg) ? P.adj[(int64_t)run_v * P.astride + lane] : -1;
             const bool bad = lane < deg && (nb < 0 || (int64_t)nb >= P.n);
             if (bad) nb = -1;
             if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
