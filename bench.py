@@ -35,7 +35,7 @@ sys.path.insert(0, str(ROOT))
 
 EPS_SWEEP = [0.0, 0.05, 0.1, 0.12, 0.14, 0.15, 0.16, 0.17, 0.18, 0.19, 0.2, 0.22, 0.25, 0.3]
 BL_EPS_STEPS = [0.0, 0.02, 0.04, 0.06]  # eps above the B operating point tried with the stop model
-L_SWEEP = [256, 1024]
+L_SWEEP = [256, 512, 1024]
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "cfg2": dict(desc="1,000,000 x 128 integer Gaussian mixture (1,000 clusters), squared L2, "

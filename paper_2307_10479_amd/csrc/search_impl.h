@@ -481,6 +481,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             if (!s_pop(S, thr0, gmin)) break;
             const float ds = key_dist(gmin);
             hops += 1;
+            // long queries set the batch's makespan: their waves get issue priority
+            if (hops == 1024) __builtin_amdgcn_s_setprio(2);
+            if (hops == 3072) __builtin_amdgcn_s_setprio(3);
 
             // learned stop / trace rows every `interval` hops
             bool want_stop = false, want_trace = false;
@@ -672,6 +675,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 P.out_dists[out_off + i] = have ? key_dist(R[r2]) : __builtin_inff();
             }
         }
+        if (hops >= 1024) __builtin_amdgcn_s_setprio(0);
         if (P.out_stats != nullptr && lane == 0) {
             int32_t *st = P.out_stats + (int64_t)qi * 4;
             st[0] = hops;
