@@ -117,3 +117,42 @@ def calibrate(store, graph, queries, seeds, k, eps, params, mean, inv_std, inter
         if best is None and agree >= 1.0 - max_loss:
             best = tau
     return (best if best is not None else 1.0), table
+
+
+def traces_from(run, n, rows, interval):
+    """Trace rows of one plain search over n queries: `run(**trace_opts)` launches it.
+    Returns (X, y) on the device (rows that received a label)."""
+    trace = torch.empty(n * rows * api.TRACE_W, dtype=torch.float32, device="cuda")
+    run(trace=trace, trace_rows=rows, trace_interval=interval)
+    T = trace.view(n * rows, api.TRACE_W)
+    keep = T[:, 16] >= 0
+    return T[keep, :16].clone(), T[keep, 16].clone()
+
+
+def agreement_flat(a_ids, b_ids, ks, offsets):
+    """Mean top-min(10, k) agreement of two flat result buffers (one k per query)."""
+    a = a_ids.cpu().numpy()
+    b = b_ids.cpu().numpy()
+    tot = 0.0
+    for k, o in zip(np.asarray(ks).tolist(), np.asarray(offsets).tolist()):
+        t = min(10, k)
+        tot += len(set(a[o:o + t].tolist()) & set(b[o:o + t].tolist())) / t
+    return tot / len(ks)
+
+
+def calibrate_flat(run_plain, run_stop, ks, offsets, params, mean, inv_std, interval,
+                   max_loss=0.005,
+                   taus=(0.5, 0.6, 0.7, 0.8, 0.85, 0.9, 0.93, 0.95, 0.97, 0.98, 0.99, 0.995)):
+    """calibrate() for a mixed stream: run_plain() and run_stop(model) return
+    (flat ids, dists, stats); the smallest tau with agreement >= 1 - max_loss wins."""
+    plain = run_plain()
+    best = None
+    table = []
+    for tau in taus:
+        got = run_stop(build_model(params, mean, inv_std, tau, interval))
+        agree = agreement_flat(got[0], plain[0], ks, offsets)
+        hops = float(got[2][:, 0].float().mean())
+        table.append((tau, agree, hops))
+        if best is None and agree >= 1.0 - max_loss:
+            best = tau
+    return (best if best is not None else 1.0), table
