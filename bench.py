@@ -310,10 +310,16 @@ def run_batch(a):
     tau, cal = stop.calibrate_flat(lambda: launch(s16, None, Dh, T),
                                    lambda mdl: launch(s16, mdl, Dh, T), hkk, hoff,
                                    params, mean, inv_std, a.stop_interval)
-    model = stop.build_model(params, mean, inv_std, tau, a.stop_interval)
-    log("stop model: %d rows (%.2f positive), loss %s, tau %.3f, calibration %s, %.1fs"
+    hold_plain = launch(s16, None, Dh, T)[0]
+    tl, lh, ltab = stop.calibrate_long(lambda mdl: launch(s16, mdl, Dh, T), hold_plain,
+                                       lambda x, y_: stop.agreement_flat(x, y_, hkk, hoff),
+                                       params, mean, inv_std, tau, a.stop_interval)
+    model = stop.build_model(params, mean, inv_std, tau, a.stop_interval, tl, lh)
+    log("stop model: %d rows (%.2f positive), loss %s, tau %.3f, calibration %s, long queries: "
+        "tau %.2f from hop %d (%s), %.1fs"
         % (X.shape[0], float(y.mean()), [round(h, 4) for h in hist], tau,
-           [(t, round(g, 4), round(h, 1)) for t, g, h in cal], time.time() - t1))
+           [(t, round(g, 4), round(h, 1)) for t, g, h in cal], tl, lh,
+           [(x[0], x[1], round(x[2], 4), round(x[3], 2)) for x in ltab], time.time() - t1))
     del X, y, T
 
     # ---- ground truth of the stream: brute force on the matrix cores (k = 100),
@@ -385,6 +391,7 @@ def run_batch(a):
         "warmup": a.warmup, "ms_per_step": head["ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
         "config": {"workload": "cfg5: %s" % WORKLOADS[name]["desc"], "tau": tau,
+                   "tau_long": tl, "long_hops": lh,
                    "stop_interval": a.stop_interval,
                    "methods": {kk_: {x: (round(v, 5) if isinstance(v, float) else v)
                                      for x, v in r_.items()} for kk_, r_ in res.items()}},
@@ -504,7 +511,7 @@ def main(argv=None):
         tau = info["tau"]
         a.stop_interval = info["interval"]
         model = stop.build_model(dev(st["params"]), dev(st["mean"]), dev(st["inv_std"]), tau,
-                                 a.stop_interval)
+                                 a.stop_interval, opBL.get("tau_long"), opBL.get("long_hops", 0))
         a.no_cpu_baseline = True
         if a.copy_mib > 0:
             cx = torch.empty(a.copy_mib << 18, dtype=torch.float32, device="cuda").fill_(1.0)
@@ -560,17 +567,26 @@ def main(argv=None):
         for eps in bl_eps:
             tau_e, cal = stop.calibrate(s16, G, Hq, hseeds, k, eps, params, mean, inv_std,
                                         a.stop_interval, queue_cap=opB["L"], **tn)
-            mdl = stop.build_model(params, mean, inv_std, tau_e, a.stop_interval)
+            # a second, lower threshold for long queries when it shortens the held-out batch
+            hold_plain = api.search(s16, G, Hq, hseeds, k, eps, queue_cap=opB["L"], **tn)[0]
+            tl, lh, ltab = stop.calibrate_long(
+                lambda mdl: api.search(s16, G, Hq, hseeds, k, eps, queue_cap=opB["L"], stop=mdl, **tn),
+                hold_plain, lambda x, y_: stop.top10_agreement(x, y_, min(10, k)),
+                params, mean, inv_std, tau_e, a.stop_interval)
+            mdl = stop.build_model(params, mean, inv_std, tau_e, a.stop_interval, tl, lh)
             row = measure("BL", eps, mdl, opB["L"])
-            row["tau"] = tau_e
+            row.update(tau=tau_e, tau_long=tl, long_hops=lh)
             rowsBL.append(row)
-            log("BL eps %.3f: tau %.3f, calibration %s, recall %.4f, %.2f ms, hops %.1f"
-                % (eps, tau_e, [(t, round(g, 4), round(h, 1)) for t, g, h in cal],
+            log("BL eps %.3f: tau %.3f, calibration %s; long queries: tau %.2f from hop %d (%s); "
+                "recall %.4f, %.2f ms, hops %.1f"
+                % (eps, tau_e, [(t, round(g, 4), round(h, 1)) for t, g, h in cal], tl, lh,
+                   [(x[0], x[1], round(x[2], 4), round(x[3], 2)) for x in ltab],
                    row["recall"], row["ms"], row["hops"]))
         ok = [x for x in rowsBL if x["recall"] >= a.recall]
         opBL = min(ok, key=lambda x: x["ms"]) if ok else max(rowsBL, key=lambda x: x["recall"])
         tau = opBL["tau"]
-        model = stop.build_model(params, mean, inv_std, tau, a.stop_interval)
+        model = stop.build_model(params, mean, inv_std, tau, a.stop_interval, opBL["tau_long"],
+                                 opBL["long_hops"])
         if a.save_state:
             info = dict(tuned=tuned, ops=dict(P=opP, B=opB, BL=opBL), tau=tau,
                         interval=a.stop_interval)
@@ -655,7 +671,8 @@ def main(argv=None):
             "workload": "%s: %s" % (a.workload, WORKLOADS[a.workload]["desc"]),
             "method": "BL: BF16 traversal + FP32 rerank + learned early stop",
             "k": k, "eps": head["eps"], "queue_cap": head["L"], "recall@10": round(head["recall"], 5),
-            "tau": tau, "stop_interval": a.stop_interval, "tuned": tuned,
+            "tau": tau, "tau_long": opBL.get("tau_long"), "long_hops": opBL.get("long_hops"),
+            "stop_interval": a.stop_interval, "tuned": tuned,
             "hops_per_query": round(head["hops"], 2), "evals_per_query": round(head["evals"], 2),
             "plain_fp32": {kk: (round(v, 5) if isinstance(v, float) else v)
                            for kk, v in res.get("P", {}).items()},

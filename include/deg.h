@@ -92,8 +92,9 @@ typedef struct {
  * Learned early stop: a 16-64-64-1 MLP (ReLU, sigmoid) in BF16 as written by
  * deg_mlp_export_bf16 (5313 values: W1[64][16], b1[64], W2[64][64], b2[64],
  * w3[64], b3). Every `interval` hops the search computes its 16 state
- * features; if sigmoid(logit) >= tau it stops. The plain rule of Algorithm 1
- * still applies.
+ * features; if sigmoid(logit) >= tau it stops (from hop `long_hops` on, when
+ * long_hops > 0, the threshold is tau_long instead: long queries set the
+ * makespan of a batch). The plain rule of Algorithm 1 still applies.
  */
 typedef struct {
     const uint16_t *weights_bf16; /* device */
@@ -101,6 +102,8 @@ typedef struct {
     const float *feat_inv_std;    /* device, 16 */
     float tau;
     int32_t interval;
+    float tau_long;               /* threshold from hop long_hops on */
+    int32_t long_hops;            /* 0 = tau throughout */
 } deg_stop_model;
 
 /* Search options. Zero-initialised means: defaults. */

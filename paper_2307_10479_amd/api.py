@@ -52,7 +52,8 @@ class DegGraph(C.Structure):
 
 class DegStopModel(C.Structure):
     _fields_ = [("weights_bf16", C.c_void_p), ("feat_mean", C.c_void_p),
-                ("feat_inv_std", C.c_void_p), ("tau", C.c_float), ("interval", C.c_int32)]
+                ("feat_inv_std", C.c_void_p), ("tau", C.c_float), ("interval", C.c_int32),
+                ("tau_long", C.c_float), ("long_hops", C.c_int32)]
 
 
 class DegSearchOpts(C.Structure):
@@ -216,13 +217,15 @@ class StopModel:
     """BF16 stop-predictor weights plus feature standardisation, on the device."""
 
     def __init__(self, weights_bf16: torch.Tensor, mean: torch.Tensor, inv_std: torch.Tensor,
-                 tau: float, interval: int):
+                 tau: float, interval: int, tau_long: float | None = None, long_hops: int = 0):
         self.w, self.mean, self.inv_std = weights_bf16, mean, inv_std
         self.tau, self.interval = float(tau), int(interval)
+        self.tau_long = float(tau if tau_long is None else tau_long)
+        self.long_hops = int(long_hops)
 
     def c(self) -> DegStopModel:
         return DegStopModel(self.w.data_ptr(), self.mean.data_ptr(), self.inv_std.data_ptr(),
-                            self.tau, self.interval)
+                            self.tau, self.interval, self.tau_long, self.long_hops)
 
 
 def _opts(queue_cap=0, hash_slots=0, k_pool=0, rerank=False, stop: StopModel | None = None,

@@ -142,11 +142,15 @@ static void fill_common(SearchParams &P, const deg_vectors *v, const deg_graph *
         P.stop_w = o->stop->weights_bf16;
         P.stop_mean = o->stop->feat_mean;
         P.stop_istd = o->stop->feat_inv_std;
-        float tau = o->stop->tau;
         // sigmoid(z) >= tau  <=>  z >= log(tau / (1 - tau))
-        P.stop_tau = tau <= 0.f ? -__builtin_inff()
-                                : (tau >= 1.f ? __builtin_inff() : logf(tau / (1.f - tau)));
+        auto logit = [](float tau) {
+            return tau <= 0.f ? -__builtin_inff()
+                              : (tau >= 1.f ? __builtin_inff() : logf(tau / (1.f - tau)));
+        };
+        P.stop_tau = logit(o->stop->tau);
         P.stop_interval = o->stop->interval;
+        P.stop_long_hops = o->stop->long_hops > 0 ? o->stop->long_hops : 0x7fffffff;
+        P.stop_tau_long = o->stop->long_hops > 0 ? logit(o->stop->tau_long) : P.stop_tau;
     }
     if (o && o->trace) {
         P.trace = o->trace;

@@ -557,7 +557,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 if (want_stop) {
                     const float fs = lane < NFEAT ? __fmul_rn(__fsub_rn(fv, f_mean), f_istd) : 0.0f;
                     const float z = mlp_logit(M, fs, hbuf);
-                    if (z >= P.stop_tau) {
+                    if (z >= (hops >= P.stop_long_hops ? P.stop_tau_long : P.stop_tau)) {
                         flags |= DEG_FLAG_LEARNED_STOP;
                         break;
                     }

@@ -86,6 +86,8 @@ struct SearchParams {
     const float *stop_istd;
     float stop_tau;
     int32_t stop_interval;
+    float stop_tau_long;
+    int32_t stop_long_hops;
     // trace
     float *trace;
     int64_t trace_rows;

@@ -87,9 +87,41 @@ def train(X, y, epochs=4, batch=8192, lr=2e-3, seed=0):
     return params, hist
 
 
-def build_model(params, mean, inv_std, tau, interval):
+def build_model(params, mean, inv_std, tau, interval, tau_long=None, long_hops=0):
     w = api.mlp_export_bf16(params)
-    return api.StopModel(w, mean, inv_std, tau, interval)
+    return api.StopModel(w, mean, inv_std, tau, interval, tau_long, long_hops)
+
+
+def calibrate_long(run, run_plain_ids, agree_fn, params, mean, inv_std, tau, interval,
+                   max_loss=0.005, long_hops=(1024, 2048, 3072),
+                   taus_long=(0.5, 0.6, 0.7, 0.8, 0.9), reps=2):
+    """Second threshold for long queries: among (long_hops, tau_long <= tau) whose
+    agreement with the plain search stays >= 1 - max_loss, the fastest on the
+    held-out queries (timed; `run(model)` launches the search, returns ids first).
+    Returns (tau_long, long_hops, table); (tau, 0) when none is faster."""
+    def timed(model):
+        run(model)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            out = run(model)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps, out
+    base_ms, _ = timed(build_model(params, mean, inv_std, tau, interval))
+    best = (tau, 0, base_ms)
+    table = [(0, tau, 1.0, base_ms)]
+    for lh in long_hops:
+        for tl in taus_long:
+            if tl >= tau:
+                continue
+            ms, out = timed(build_model(params, mean, inv_std, tau, interval, tl, lh))
+            agree = agree_fn(out[0], run_plain_ids)
+            table.append((lh, tl, agree, ms))
+            if agree >= 1.0 - max_loss and ms < best[2]:
+                best = (tl, lh, ms)
+    return best[0], best[1], table
 
 
 def top10_agreement(a_ids, b_ids, k=10):

@@ -345,6 +345,17 @@ def test_learned_stop_extremes(A):
     stopped = (sa[:, 2] & A.FLAG_LEARNED_STOP) != 0
     assert (sa[stopped, 0] == 3).all()
     assert (sa[~stopped, 0] == sp[~stopped, 0]).all() and (sp[~stopped, 0] < 3).all()
+    # never before hop H, always from hop H on (H a checkpoint: a multiple of 3)
+    H = 3 * int(np.median(sp[:, 0]) // 3)
+    late = A.search(store, g, dev(q), seeds, 10, 0.1,
+                    stop=A.StopModel(w, mean, istd, 1.0, 3, tau_long=0.0, long_hops=H))
+    torch.cuda.synchronize()
+    sl = late[2].cpu().numpy()
+    long_q = sp[:, 0] >= H
+    assert long_q.any() and (~long_q).any()
+    assert (sl[long_q, 0] == H).all() and ((sl[long_q, 2] & A.FLAG_LEARNED_STOP) != 0).all()
+    assert (sl[~long_q, 0] == sp[~long_q, 0]).all()
+    assert (late[0].cpu().numpy()[~long_q] == plain[0].cpu().numpy()[~long_q]).all()
 
 
 def test_hip_graph_capture_replays(A):
