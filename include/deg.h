@@ -91,8 +91,12 @@ typedef struct {
 /*
  * Learned early stop: a 16-64-64-1 MLP (ReLU, sigmoid) in BF16 as written by
  * deg_mlp_export_bf16 (5313 values: W1[64][16], b1[64], W2[64][64], b2[64],
- * w3[64], b3). Every `interval` hops the search computes its 16 state
- * features; if sigmoid(logit) >= tau it stops (from hop `long_hops` on, when
+ * w3[64], b3), evaluated with BF16 weights, the inputs of both hidden layers
+ * rounded to BF16 and FP32 accumulation. Every `interval` hops the search
+ * computes its 16 state features (hop and evaluation counts, best/k-th and
+ * radius ratios, stagnation counters, acceptance fractions, queued candidates
+ * closer than the k-th result, popped over k-th distance, eps, k, kind,
+ * visited count); if sigmoid(logit) >= tau it stops (from hop `long_hops` on, when
  * long_hops > 0, the threshold is tau_long instead: long queries set the
  * makespan of a batch). The plain rule of Algorithm 1 still applies.
  */
@@ -108,8 +112,12 @@ typedef struct {
 
 /* Search options. Zero-initialised means: defaults. */
 typedef struct {
-    int32_t queue_cap;  /* capacity L of the candidate set S; 0 = default max(256, 8 k_pool) */
-    int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = default */
+    int32_t queue_cap;  /* capacity L of the candidate set S, applied at the end of each hop:
+                           when |S| > L + 64 the entries beyond the threshold r(1+eps) are
+                           dropped, then if still |S| > L + 64 only the L smallest stay
+                           (DEG_FLAG_QUEUE_OVERFLOW); 0 = default max(256, 8 k_pool) */
+    int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = tuned or
+                           default. The set moves to a workspace table at 3/4 load. */
     int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
                            from f32_data when k_pool > k or dtype != DEG_F32; 0 = k */
     int32_t rerank;     /* 1 = always rerank the pool in FP32, 0 = only when needed */
@@ -183,11 +191,12 @@ deg_status deg_search_batch(const deg_vectors *v, const deg_graph *g, const floa
 
 /*
  * Exact k nearest neighbours (Eq. knn) by brute force on matrix cores.
- * BF16 products with FP32 accumulation find candidates (exact for
- * integer-valued data below 256); the best k + margin per query are then
- * recomputed as direct FP32 differences in the C32x4 order and sorted by
- * (distance, id). exclude_ids: nullable, one id per query kept out of its
- * result (exploratory ground truth).
+ * FP32 matrix products (v_mfma_f32_32x32x2f32) of the norm expansion find
+ * candidates (exact for integer-valued data below 256); the best k + margin
+ * per query are then recomputed as direct FP32 differences in the C32x4 order
+ * and sorted by (distance, id). exclude_ids: nullable, one id per query kept
+ * out of its result (exploratory ground truth). base rows are read as float4:
+ * b_stride must be a multiple of 4.
  */
 size_t deg_knn_workspace_bytes(int64_t n, int32_t dim, int64_t nq, int32_t k);
 deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t dim, int64_t b_stride,
