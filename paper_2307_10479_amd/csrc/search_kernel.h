@@ -273,17 +273,21 @@ __device__ __forceinline__ float half_reduce(float a) {
 // unconditionally (lanes without work read a valid chunk and are masked to
 // zero afterwards), so that all loads are in flight before any is decoded.
 // F32ROWS reads the FP32 rows (rerank) instead of the traversal store.
-template <int DT, int METRIC, int QCH, bool F32ROWS = false>
-__device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
-                                            int32_t cand, uint64_t mask, int nch, bool mask_tail) {
-    constexpr int DL = F32ROWS ? DT_F32 : DT;
-    // rows in flight per half-wave: a register budget for the raw chunks, so
-    // that narrower storage keeps more rows (and memory requests) in flight
+// Rows in flight per half-wave at most: a register budget for the raw chunks,
+// so that narrower storage keeps more rows (and memory requests) in flight.
+template <int DL, int QCH>
+constexpr int dist_rounds_max() {
     constexpr int WPC = DL == DT_F32 ? 4 : (DL == DT_BF16 ? 2 : 1);  // 32-bit words per chunk
     constexpr int BUDGET = QCH >= 12 ? 96 : 32;
     constexpr int G0 = BUDGET / (QCH * WPC);
     constexpr int GMAX = QCH >= 12 ? 4 : 8;
-    constexpr int G = G0 < 1 ? 1 : (G0 > GMAX ? GMAX : G0);
+    return G0 < 1 ? 1 : (G0 > GMAX ? GMAX : G0);
+}
+
+template <int DT, int METRIC, int QCH, bool F32ROWS, int G>
+__device__ __forceinline__ float batch_dist_g(const SearchParams &P, const float4 (&qv)[QCH],
+                                              int32_t cand, uint64_t mask, int nch, bool mask_tail) {
+    constexpr int DL = F32ROWS ? DT_F32 : DT;
     using Raw = typename RawChunk<DL>::T;
     const int lane = lane_id();
     const int half = lane >> 5, p = lane & 31;
@@ -344,6 +348,20 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
         }
     }
     return res;
+}
+
+// Distances of the lanes in `mask` (candidate id in `cand`): the number of
+// rows loaded per round follows the number of candidates (2 per round and
+// half-wave pair), so that a hop with few new neighbours issues few loads.
+template <int DT, int METRIC, int QCH, bool F32ROWS = false>
+__device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
+                                            int32_t cand, uint64_t mask, int nch, bool mask_tail) {
+    constexpr int GM = dist_rounds_max<F32ROWS ? DT_F32 : DT, QCH>();
+    const int cnt = __popcll(mask);
+    if (GM >= 2 && cnt <= 2) return batch_dist_g<DT, METRIC, QCH, F32ROWS, 1>(P, qv, cand, mask, nch, mask_tail);
+    if (GM >= 4 && cnt <= 4) return batch_dist_g<DT, METRIC, QCH, F32ROWS, 2>(P, qv, cand, mask, nch, mask_tail);
+    if (GM >= 8 && cnt <= 8) return batch_dist_g<DT, METRIC, QCH, F32ROWS, 4>(P, qv, cand, mask, nch, mask_tail);
+    return batch_dist_g<DT, METRIC, QCH, F32ROWS, GM>(P, qv, cand, mask, nch, mask_tail);
 }
 
 // ---------------------------------------------------------------- visited set
