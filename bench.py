@@ -632,6 +632,20 @@ def main(argv=None):
         log("%-2s L %d eps %.3f recall %.4f  %.3f ms/step  %.0f QPS  hops %.1f evals %.1f  %.0f GB/s"
             % (name, op["L"], op["eps"], r, ms, res[name]["qps"], hops / nq, evals / nq, res[name]["gbs"]))
 
+    # ---- k = 100 (recall@10 of the first 10 of 100 results): P and B
+    k100 = {}
+    if not a.profile and a.workload == "cfg2":
+        for name_, store_ in (("P", s32), ("B", s16)):
+            for eps in EPS_SWEEP:
+                tn = tuned.get("P" if name_ == "P" else "B", {})
+                fn = (lambda e=eps: api.search(store_, G, Q, seeds, 100, e, queue_cap=1024, **tn))
+                ms, (ids, ds, st) = _timed_launch(torch, fn, 1, 3)
+                r = metrics.recall_at_k(ids[:, :10].cpu().numpy(), gt, 10)
+                if r >= a.recall:
+                    k100[name_] = dict(eps=eps, recall_at_10=round(r, 5), ms=round(ms, 3),
+                                       qps=round(nq / (ms / 1e3), 1))
+                    log("k=100 %s: eps %.2f recall@10 %.4f %.3f ms %.0f QPS" % (name_, eps, r, ms, nq / (ms / 1e3)))
+                    break
     head_name = "BL" if "BL" in res else next(iter(res))
     head = res[head_name]
     # ---- CPU baseline: the oracle's Algorithm 1 on a bounded sample, all host threads
@@ -652,6 +666,17 @@ def main(argv=None):
                    sample="first %d of the %d queries, plain FP32 Algorithm 1 at eps=%g, k=%d"
                           % (sample, nq, opP["eps"], k))
         log("cpu oracle: %d queries in %.1fs on %d threads = %.0f QPS" % (sample, dt, thr, sample / dt))
+        # one thread on 1,000 queries (the paper's protocol), and the host CPU model
+        s1 = min(nq, 1000)
+        t2 = time.time()
+        oracle.range_search(base, adj, q[:s1], [seed], k, opP["eps"], metric, nthreads=1)
+        cpu["single_thread_qps"] = s1 / (time.time() - t2)
+        try:
+            cpu["model"] = next(l.split(":", 1)[1].strip() for l in open("/proc/cpuinfo")
+                                if l.startswith("model name"))
+        except (OSError, StopIteration):
+            cpu["model"] = None
+        log("cpu oracle: one thread %.0f QPS (%s)" % (cpu["single_thread_qps"], cpu["model"]))
 
     out = {
         "metric": "QPS @ recall@10>=0.95, 1M x 128 L2: BF16+learned-stop vs plain FP32"
@@ -679,6 +704,7 @@ def main(argv=None):
             "bf16_rerank": {kk: (round(v, 5) if isinstance(v, float) else v)
                             for kk, v in res.get("B", {}).items()},
             "bl_over_plain_qps": (res["BL"]["qps"] / res["P"]["qps"]) if "BL" in res and "P" in res else None,
+            "k100": k100,
         },
         "roofline": {
             "bound": "hbm", "achieved": round(head["gbs"], 1), "peak": HBM_PEAK_GBS,
