@@ -564,27 +564,31 @@ def main(argv=None):
         # calibrated on held-out training queries (top-10 loss against the plain
         # search at that eps <= 0.5%); the fastest with recall@10 >= target wins
         rowsBL = []
-        for eps in bl_eps:
-            tau_e, cal = stop.calibrate(s16, G, Hq, hseeds, k, eps, params, mean, inv_std,
-                                        a.stop_interval, queue_cap=opB["L"], **tn)
-            # a second, lower threshold for long queries when it shortens the held-out batch
-            hold_plain = api.search(s16, G, Hq, hseeds, k, eps, queue_cap=opB["L"], **tn)[0]
-            tl, lh, ltab = stop.calibrate_long(
-                lambda mdl: api.search(s16, G, Hq, hseeds, k, eps, queue_cap=opB["L"], stop=mdl, **tn),
-                hold_plain, lambda x, y_: stop.top10_agreement(x, y_, min(10, k)),
-                params, mean, inv_std, tau_e, a.stop_interval)
-            mdl = stop.build_model(params, mean, inv_std, tau_e, a.stop_interval, tl, lh)
-            row = measure("BL", eps, mdl, opB["L"])
-            row.update(tau=tau_e, tau_long=tl, long_hops=lh)
-            rowsBL.append(row)
-            log("BL eps %.3f: tau %.3f, calibration %s; long queries: tau %.2f from hop %d (%s); "
-                "recall %.4f, %.2f ms, hops %.1f"
-                % (eps, tau_e, [(t, round(g, 4), round(h, 1)) for t, g, h in cal], tl, lh,
-                   [(x[0], x[1], round(x[2], 4), round(x[3], 2)) for x in ltab],
-                   row["recall"], row["ms"], row["hops"]))
+        # the network is checked every `interval` hops; a sparser check costs less
+        # and stops later, so both the trained interval and twice it are tried
+        for itv in (a.stop_interval, 2 * a.stop_interval):
+            for eps in bl_eps:
+                tau_e, cal = stop.calibrate(s16, G, Hq, hseeds, k, eps, params, mean, inv_std,
+                                            itv, queue_cap=opB["L"], **tn)
+                # a second, lower threshold for long queries when it shortens the held-out batch
+                hold_plain = api.search(s16, G, Hq, hseeds, k, eps, queue_cap=opB["L"], **tn)[0]
+                tl, lh, ltab = stop.calibrate_long(
+                    lambda mdl: api.search(s16, G, Hq, hseeds, k, eps, queue_cap=opB["L"], stop=mdl,
+                                           **tn),
+                    hold_plain, lambda x, y_: stop.top10_agreement(x, y_, min(10, k)),
+                    params, mean, inv_std, tau_e, itv)
+                mdl = stop.build_model(params, mean, inv_std, tau_e, itv, tl, lh)
+                row = measure("BL", eps, mdl, opB["L"])
+                row.update(tau=tau_e, tau_long=tl, long_hops=lh, interval=itv)
+                rowsBL.append(row)
+                log("BL interval %d eps %.3f: tau %.3f, calibration %s; long queries: tau %.2f from "
+                    "hop %d; recall %.4f, %.2f ms, hops %.1f"
+                    % (itv, eps, tau_e, [(t, round(g, 4), round(h, 1)) for t, g, h in cal], tl, lh,
+                       row["recall"], row["ms"], row["hops"]))
         ok = [x for x in rowsBL if x["recall"] >= a.recall]
         opBL = min(ok, key=lambda x: x["ms"]) if ok else max(rowsBL, key=lambda x: x["recall"])
         tau = opBL["tau"]
+        a.stop_interval = opBL["interval"]
         model = stop.build_model(params, mean, inv_std, tau, a.stop_interval, opBL["tau_long"],
                                  opBL["long_hops"])
         if a.save_state:

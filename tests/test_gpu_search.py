@@ -199,6 +199,24 @@ def test_parity_large_ids_small_table(A, n):
     assert ((got[2][:, 2] & A.FLAG_HASH_SPILL) != 0).any()
 
 
+def test_parity_unpadded_adjacency(A):
+    """The same search over the adjacency in its given layout (rows of exactly
+    `degree` ids) and padded to 128-byte rows."""
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 73, 100, 24)
+    say("adjacency layouts")
+    store = A.VectorStore(dev(x), "f32")
+    outs = []
+    for align in (1, 32):
+        g = A.DeviceGraph(dev(adj), row_align=align)
+        assert g.stride == (30 if align == 1 else 32)
+        outs.append([t.cpu().numpy() for t in A.search(store, g, dev(q), dev(np.zeros((100, 1), np.int32)), 10, 0.2)])
+    for u, v in zip(*outs):
+        assert (u == v).all()
+    ref = oracle.range_search(x, adj, q, [0], 10, 0.2, cap_L=max(256, 8 * 10))
+    assert_parity(tuple(outs[0]), ref, "unpadded")
+
+
 def test_parity_indexed(A):
     x, adj = graph(1500, 100, 30, "unit", oracle.IP)
     qids = synth.rng(61).choice(1500, size=200, replace=False).astype(np.int32)
