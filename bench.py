@@ -403,6 +403,42 @@ def run_batch(a):
     return 0
 
 
+def run_knn(a):
+    """Brute-force ground truth on the matrix cores for the 10,000 queries of the
+    1M x 128 workload (k = 100), against the stored FP64 ground truth."""
+    import torch
+
+    import synth
+    from paper_2307_10479_amd import api
+    api.lib()
+    torch.cuda.set_device(0)
+    base, q = synth.cfg2()
+    gt = np.load(ROOT / "data" / "cfg2.gt.npz")
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    xb, Q = dev(base), dev(q)
+    n, m = base.shape
+    nq, k = q.shape[0], 100
+    ms, (ids, ds) = _timed_launch(torch, lambda: api.knn_bruteforce(xb, Q, k), a.warmup, a.steps)
+    ids = ids.cpu().numpy()
+    exact = float((ids == gt["ids"]).all(axis=1).mean())
+    flops = 2.0 * n * nq * m
+    tfs = flops / (ms / 1e3) / 1e12
+    log("knn: %.3f ms, %.1f TFLOP/s, rows identical to the FP64 ground truth: %.4f" % (ms, tfs, exact))
+    out = {
+        "metric": "brute-force exact kNN (k=100) of 10,000 queries against 1M x 128",
+        "value": nq / (ms / 1e3), "unit": "queries/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "cfg2 ground truth: 1,000,000 x 128 integer mixture, 10,000 queries, k=100",
+                   "rows_equal_to_fp64_ground_truth": exact},
+        "roofline": {"bound": "mfma", "achieved": round(tfs, 2), "peak": 157.3, "unit": "TFLOP/s",
+                     "frac": round(tfs / 157.3, 4), "traffic": None},
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,6 +458,8 @@ def main(argv=None):
                     help="write the operating points, launch tuning and stop model to this .npz")
     ap.add_argument("--profile", default="",
                     help="profile mode: load a --save-state file and run only the timed steps")
+    ap.add_argument("--knn", action="store_true",
+                    help="time the brute-force ground truth (matrix cores) instead of the search")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="profile mode: first copy this many MiB device-to-device (counter calibration)")
     a = ap.parse_args(argv)
@@ -430,6 +468,8 @@ def main(argv=None):
               "and splitting the queries, but only --gpus 1 is measured here", file=sys.stderr)
         return 2
 
+    if a.knn:
+        return run_knn(a)
     if a.workload in ("cfg3", "cfg4"):
         return run_secondary(a)
     if a.workload == "cfg5":
