@@ -106,6 +106,68 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
         cnt[t] = 0;
     }
     __syncthreads();
+    // Staging of one (tile, chunk): the thread's 8 query values (row t % 64,
+    // dims 8 (t / 64) ..) and 16 base values (row t % 128, dims 16 (t / 128) ..)
+    // are read into registers one chunk ahead (while the matrix cores work on
+    // the current one, and across the epilogue), then written to LDS.
+    float4 rq[2], rb[4];
+    auto fetch = [&](int64_t bt, int k0) {
+        {
+            const int r = t & 63, dq = (t >> 6) * 8;
+            const int64_t qi = q0 + r;
+            if (qi < P.nq && k0 + dq + 8 <= P.dim && (P.qstride & 3) == 0) {
+                const float4 *src = reinterpret_cast<const float4 *>(P.queries + qi * P.qstride + k0 + dq);
+                rq[0] = src[0];
+                rq[1] = src[1];
+            } else {
+                float v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const int c = k0 + dq + j;
+                    v[j] = (qi < P.nq && c < P.dim) ? P.queries[qi * P.qstride + c] : 0.0f;
+                }
+                rq[0] = make_float4(v[0], v[1], v[2], v[3]);
+                rq[1] = make_float4(v[4], v[5], v[6], v[7]);
+            }
+        }
+        {
+            const int r = t & 127, dq = (t >> 7) * 16;
+            const int64_t bi = bt + r;
+            if (bi < n1 && k0 + dq + 16 <= P.dim) {  // rows are 16-byte aligned (b_stride % 4 == 0)
+                const float4 *src = reinterpret_cast<const float4 *>(P.base + bi * P.bstride + k0 + dq);
+#pragma unroll
+                for (int j4 = 0; j4 < 4; ++j4) rb[j4] = src[j4];
+            } else {
+                float v[16];
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int c = k0 + dq + j;
+                    v[j] = (bi < n1 && c < P.dim) ? P.base[bi * P.bstride + c] : 0.0f;
+                }
+#pragma unroll
+                for (int j4 = 0; j4 < 4; ++j4)
+                    rb[j4] = make_float4(v[4 * j4], v[4 * j4 + 1], v[4 * j4 + 2], v[4 * j4 + 3]);
+            }
+        }
+    };
+    auto stage = [&]() {
+        {
+            const int r = t & 63, dq = (t >> 6) * 8;
+            QsT[dq + 0][r] = rq[0].x; QsT[dq + 1][r] = rq[0].y; QsT[dq + 2][r] = rq[0].z; QsT[dq + 3][r] = rq[0].w;
+            QsT[dq + 4][r] = rq[1].x; QsT[dq + 5][r] = rq[1].y; QsT[dq + 6][r] = rq[1].z; QsT[dq + 7][r] = rq[1].w;
+        }
+        {
+            const int r = t & 127, dq = (t >> 7) * 16;
+#pragma unroll
+            for (int j4 = 0; j4 < 4; ++j4) {
+                BsT[dq + 4 * j4 + 0][r] = rb[j4].x;
+                BsT[dq + 4 * j4 + 1][r] = rb[j4].y;
+                BsT[dq + 4 * j4 + 2][r] = rb[j4].z;
+                BsT[dq + 4 * j4 + 3][r] = rb[j4].w;
+            }
+        }
+    };
+    if (n0 < n1) fetch(n0, 0);
     for (int64_t b0 = n0; b0 < n1; b0 += KN) {
         floatx16 acc0, acc1;
 #pragma unroll
@@ -114,27 +176,13 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
             acc1[v] = 0.0f;
         }
         for (int k0 = 0; k0 < P.dim; k0 += KCH) {
-            // queries: 64 rows x 32 dims; thread -> row t % 64, dims 8*(t/64) .. +7
-            {
-                int r = t & 63, dq = (t >> 6) * 8;
-                int64_t qi = q0 + r;
-#pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    int c = k0 + dq + j;
-                    QsT[dq + j][r] = (qi < P.nq && c < P.dim) ? P.queries[qi * P.qstride + c] : 0.0f;
-                }
-            }
-            // base: 128 rows x 32 dims; thread -> row t % 128, dims 16*(t/128) .. +15
-            {
-                int r = t & 127, dq = (t >> 7) * 16;
-                int64_t bi = b0 + r;
-#pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    int c = k0 + dq + j;
-                    BsT[dq + j][r] = (bi < n1 && c < P.dim) ? P.base[bi * P.bstride + c] : 0.0f;
-                }
-            }
+            stage();
             __syncthreads();
+            // the next chunk of this tile, or the first chunk of the next tile
+            if (k0 + KCH < P.dim)
+                fetch(b0, k0 + KCH);
+            else if (b0 + KN < n1)
+                fetch(b0 + KN, 0);
 #pragma unroll
             for (int kk = 0; kk < KCH; kk += 2) {
                 int kr = kk + (lane >> 5);
@@ -155,12 +203,25 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
             S[row][col + 32] = acc1[v];
         }
         __syncthreads();
-        // epilogue: wave w takes query rows 16w .. 16w+15
+        // epilogue: wave w takes query rows 16w .. 16w+15; the base norms of the
+        // tile's columns and the rows' query norms are read once per tile
+        float bn[2] = {0.f, 0.f};
+        if (METRIC == DEG_METRIC_L2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int64_t bi = b0 + lane + 64 * h;
+                bn[h] = P.bnorm[bi < n1 ? bi : 0];
+            }
+        }
+        const int64_t qrow0 = q0 + w * 16 + (lane & 15);
+        const float qn_l = (METRIC == DEG_METRIC_L2 && qrow0 < P.nq) ? P.qnorm[qrow0] : 0.f;
+        const int32_t ex_l = (P.exclude && qrow0 < P.nq) ? P.exclude[qrow0] : -1;
         for (int rr = 0; rr < 16; ++rr) {
             int row = w * 16 + rr;
             int64_t qi = q0 + row;
             if (qi >= P.nq) break;
-            int32_t ex = P.exclude ? P.exclude[qi] : -1;
+            const int32_t ex = __builtin_amdgcn_readlane(ex_l, rr);
+            const float qn = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qn_l), rr));
             uint64_t th = thr[row];
             uint64_t key[2];
             bool pass[2];
@@ -171,7 +232,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
                 float dot = S[row][col];
                 float d;
                 if (METRIC == DEG_METRIC_L2)
-                    d = __fsub_rn(__fadd_rn(P.qnorm[qi], P.bnorm[bi < n1 ? bi : 0]), __fmul_rn(2.0f, dot));
+                    d = __fsub_rn(__fadd_rn(qn, bn[h]), __fmul_rn(2.0f, dot));
                 else
                     d = __fsub_rn(1.0f, dot);
                 key[h] = make_key(d, (int32_t)bi);
