@@ -52,38 +52,41 @@ __global__ void row_norm_kernel(const float *x, int64_t n, int32_t dim, int64_t 
     out[i] = s;
 }
 
-// KC-th smallest of `cnt` distinct keys held in `buf` (global), by one wave.
-__device__ uint64_t select_kth(const uint64_t *buf, int cnt, int kc) {
+// Cuts the `cnt` distinct keys of `buf` (global, one wave) to the kc smallest:
+// the keys are read once into registers (up to SEL_R per lane), the kc-th
+// smallest is built bit by bit from the top by counting the keys below each
+// candidate prefix, and the kept keys are written back compacted. Returns the
+// kc-th key; `cnt` becomes kc (or stays, if cnt <= kc).
+constexpr int SEL_R = 20;  // covers cap = 2 (k + 32) + 128 for k <= 512
+__device__ uint64_t cut_list(uint64_t *buf, int &cnt, int kc) {
     const int lane = lane_id();
+    uint64_t v[SEL_R];
+#pragma unroll
+    for (int r = 0; r < SEL_R; ++r) {
+        const int i = lane + WAVE * r;
+        v[r] = i < cnt ? buf[i] : KEY_MAX;
+    }
     uint64_t ans = 0;
     for (int b = 63; b >= 0; --b) {
-        uint64_t cand = ans | (1ull << b);
+        const uint64_t cand = ans | (1ull << b);
         int c = 0;
-        for (int i = lane; i < cnt; i += WAVE) c += buf[i] < cand ? 1 : 0;
+#pragma unroll
+        for (int r = 0; r < SEL_R; ++r) c += v[r] < cand ? 1 : 0;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
         if (c < kc) ans = cand;
     }
-    return ans;
-}
-
-// Keeps the keys <= kth (in place, order kept); returns the new count.
-__device__ int keep_le(uint64_t *buf, int cnt, uint64_t kth) {
-    const int lane = lane_id();
     int out = 0;
-    for (int base = 0; base < cnt; base += WAVE) {
-        int i = base + lane;
-        uint64_t v = i < cnt ? buf[i] : KEY_MAX;
-        bool keep = i < cnt && v <= kth;
-        uint64_t m = ballot(keep);
-        __builtin_amdgcn_s_waitcnt(0);
-        wave_sync();
-        if (keep) buf[out + prefix_in(m)] = v;
+#pragma unroll
+    for (int r = 0; r < SEL_R; ++r) {
+        const int i = lane + WAVE * r;
+        const bool keep = i < cnt && v[r] <= ans;
+        const uint64_t m = ballot(keep);
+        if (keep) buf[out + prefix_in(m)] = v[r];
         out += __popcll(m);
-        __threadfence_block();
-        wave_sync();
     }
-    return out;
+    cnt = out;
+    return ans;
 }
 
 template <int METRIC>
@@ -249,9 +252,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
             if (c > P.cap - KN) {
                 __threadfence_block();
                 wave_sync();
-                uint64_t kth = select_kth(lst, c, P.kc);
-                c = keep_le(lst, c, kth);
-                th = kth;
+                th = cut_list(lst, c, P.kc);
             }
             if (lane == 0) {
                 cnt[row] = c;
@@ -269,10 +270,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
         int c = cnt[row];
         __threadfence_block();
         wave_sync();
-        if (c > P.kc) {
-            uint64_t kth = select_kth(lst, c, P.kc);
-            c = keep_le(lst, c, kth);
-        }
+        if (c > P.kc) cut_list(lst, c, P.kc);
         if (lane == 0) P.counts[qi * P.nslices + slice] = c;
     }
 }
