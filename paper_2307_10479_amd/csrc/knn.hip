@@ -94,8 +94,6 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
     __shared__ float QsT[KCH][KQ + 1];
     __shared__ float BsT[KCH][KN + 1];
     __shared__ float S[KQ][KN + 1];
-    __shared__ uint64_t thr[KQ];
-    __shared__ int cnt[KQ];
     const int t = threadIdx.x;
     const int w = t >> 6, lane = t & 63;
     const int wq = w >> 1, wn = w & 1;
@@ -104,11 +102,10 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
     const int64_t per = (P.n + P.nslices - 1) / P.nslices;
     const int64_t n0 = (int64_t)slice * per;
     const int64_t n1 = min(P.n, n0 + per);
-    if (t < KQ) {
-        thr[t] = KEY_MAX;
-        cnt[t] = 0;
-    }
-    __syncthreads();
+    // wave w owns query rows 16w .. 16w+15: lane r < 16 keeps row 16w + r's
+    // list threshold and count in registers
+    uint64_t thr_l = KEY_MAX;
+    int cnt_l = 0;
     // Staging of one (tile, chunk): the thread's 8 query values (row t % 64,
     // dims 8 (t / 64) ..) and 16 base values (row t % 128, dims 16 (t / 128) ..)
     // are read into registers one chunk ahead (while the matrix cores work on
@@ -225,7 +222,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
             if (qi >= P.nq) break;
             const int32_t ex = __builtin_amdgcn_readlane(ex_l, rr);
             const float qn = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qn_l), rr));
-            uint64_t th = thr[row];
+            uint64_t th = read_lane_u64(thr_l, rr);
             uint64_t key[2];
             bool pass[2];
 #pragma unroll
@@ -242,7 +239,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
                 pass[h] = bi < n1 && bi != ex && key[h] < th;
             }
             uint64_t *lst = P.lists + ((int64_t)qi * P.nslices + slice) * P.cap;
-            int c = cnt[row];
+            int c = __builtin_amdgcn_readlane(cnt_l, rr);
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 uint64_t m = ballot(pass[h]);
@@ -254,9 +251,9 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
                 wave_sync();
                 th = cut_list(lst, c, P.kc);
             }
-            if (lane == 0) {
-                cnt[row] = c;
-                thr[row] = th;
+            if (lane == rr) {
+                cnt_l = c;
+                thr_l = th;
             }
         }
         __syncthreads();
@@ -267,7 +264,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
         int64_t qi = q0 + row;
         if (qi >= P.nq) break;
         uint64_t *lst = P.lists + ((int64_t)qi * P.nslices + slice) * P.cap;
-        int c = cnt[row];
+        int c = __builtin_amdgcn_readlane(cnt_l, rr);
         __threadfence_block();
         wave_sync();
         if (c > P.kc) cut_list(lst, c, P.kc);
