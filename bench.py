@@ -295,7 +295,8 @@ def run_batch(a):
     T = dev(train)
     rng = np.random.default_rng(54)
     tk, tsv, trows, tkk, tee = _stream(rng, ntr - nhold, ntr - nhold, n, seed)
-    Dt = api.make_descs(tk, tsv, trows, tkk, tee)
+    dt_, tot_t, km_t = api.make_descs(tk, tsv, trows, tkk, tee)
+    Dt = (dt_, len(tk), tot_t, km_t)
     X, y = stop.traces_from(lambda **o: launch(s16, None, Dt, T, **o), ntr - nhold, 256,
                             a.stop_interval)
     if X.shape[0] > 8_000_000:
@@ -305,7 +306,8 @@ def run_batch(a):
     params, hist = stop.train(((X - mean) * inv_std).contiguous(), y.contiguous(), epochs=a.epochs)
     hk, hsv, hrows, hkk, hee = _stream(rng, nhold, nhold, n, seed)
     hrows = hrows + (ntr - nhold)  # held-out vectors
-    Dh = api.make_descs(hk, hsv, hrows, hkk, hee)
+    dh_, tot_h, km_h = api.make_descs(hk, hsv, hrows, hkk, hee)
+    Dh = (dh_, nhold, tot_h, km_h)
     hoff = np.concatenate([[0], np.cumsum(hkk)[:-1]])
     tau, cal = stop.calibrate_flat(lambda: launch(s16, None, Dh, T),
                                    lambda mdl: launch(s16, mdl, Dh, T), hkk, hoff,
