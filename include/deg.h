@@ -115,7 +115,7 @@ typedef struct {
     int32_t queue_cap;  /* capacity L of the candidate set S, applied at the end of each hop:
                            when |S| > L + 64 the entries beyond the threshold r(1+eps) are
                            dropped, then if still |S| > L + 64 only the L smallest stay
-                           (DEG_FLAG_QUEUE_OVERFLOW); 0 = default max(256, 8 k_pool) */
+                           (DEG_FLAG_QUEUE_OVERFLOW); 0 = default min(4096, max(256, 8 k_pool)) */
     int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = tuned or
                            default. The set moves to a workspace table at 3/4 load. */
     int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
@@ -140,7 +140,8 @@ size_t deg_search_workspace_bytes(const deg_vectors *v, const deg_graph *g, int6
  *   queries   nq rows of q_stride FP32 (dim used)
  *   seed_ids  nq x n_seeds distinct seed vertices (Sec. 5.4: the search starts
  *             from the graph's median vertex, see deg_medoid)
- *   k         results per query (1..512), eps >= 0 the range factor
+ *   k         results per query (1..1024; up to 512 with a stop model or trace
+ *             rows), eps >= 0 the range factor
  *   out_ids   nq x k int32, out_dists nq x k FP32 (the traversal distance, or
  *             the FP32 distance after a rerank)
  *   out_stats nullable; nq x 4 int32 {hops, distance evaluations, flags, 0}

@@ -46,10 +46,11 @@ static deg_status validate_common(const deg_vectors *v, const deg_graph *g, int3
     if (((v->dim + 3) / 4 + 31) / 32 > 12) return DEG_ERR_UNSUPPORTED;
     if (g->degree < 4 || (g->degree & 1) || g->degree > 64 || g->row_stride < g->degree)
         return DEG_ERR_INVALID_ARG;
-    if (kmax < 1 || kmax > 512) return DEG_ERR_INVALID_ARG;
+    if (kmax < 1 || kmax > 1024) return DEG_ERR_INVALID_ARG;
     int kp = kmax;
     if (o && o->k_pool > kp) kp = o->k_pool;
-    if (kp > 512) return DEG_ERR_INVALID_ARG;
+    if (kp > 1024) return DEG_ERR_INVALID_ARG;
+    if (kp > 512 && o && (o->stop || o->trace)) return DEG_ERR_UNSUPPORTED;  // stop features: k <= 512
     bool rerank = v->dtype != DEG_F32 || (o && (o->rerank || o->k_pool > kmax));
     if ((rerank || need_f32) && !v->f32_data) return DEG_ERR_INVALID_ARG;
     if (v->f32_data && (v->f32_stride < v->dim || (v->f32_stride & 3))) return DEG_ERR_INVALID_ARG;
@@ -72,11 +73,12 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     LaunchCfg c;
     int kp = kmax;
     if (o && o->k_pool > kp) kp = o->k_pool;
-    c.rreg = kp <= 64 ? 1 : (kp <= 128 ? 2 : (kp <= 256 ? 4 : 8));
+    c.rreg = kp <= 64 ? 1 : (kp <= 128 ? 2 : (kp <= 256 ? 4 : (kp <= 512 ? 8 : 16)));
     int nch = (v->dim + 3) / 4;
     int q = (nch + 31) / 32;
     c.qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
-    int L = (o && o->queue_cap > 0) ? o->queue_cap : (8 * kp > 256 ? 8 * kp : 256);
+    int L = (o && o->queue_cap > 0) ? o->queue_cap
+                                    : (8 * kp > 4096 ? 4096 : (8 * kp > 256 ? 8 * kp : 256));
     c.L = L;
     c.scap = ((L + 192 > kp ? L + 192 : kp) + 63) / 64 * 64;  // B (L + 64 + two pushes) / rerank buffer
     const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);

@@ -702,7 +702,8 @@ static KernelFn pick_r(int rreg, bool feat) {
         case 1: return search_kernel<DT, METRIC, QCH, 1, false>;
         case 2: return search_kernel<DT, METRIC, QCH, 2, false>;
         case 4: return search_kernel<DT, METRIC, QCH, 4, false>;
-        default: return search_kernel<DT, METRIC, QCH, 8, false>;
+        case 8: return search_kernel<DT, METRIC, QCH, 8, false>;
+        default: return search_kernel<DT, METRIC, QCH, 16, false>;
     }
 }
 template <int DT, int METRIC>

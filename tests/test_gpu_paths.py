@@ -96,7 +96,7 @@ def test_bf16_lossless_on_integer_data(A):
                                                  ("bf16", "unit", oracle.IP, 100),
                                                  ("fp8", "sparse", oracle.L2, 137),
                                                  ("fp8", "float", oracle.L2, 300)])
-@pytest.mark.parametrize("k,pool", [(10, 10), (10, 40), (100, 200)])
+@pytest.mark.parametrize("k,pool", [(10, 10), (10, 40), (100, 200), (300, 1000)])
 def test_reduced_precision_with_rerank_matches_oracle(A, dtype, kind, metric, m, k, pool):
     """Traversal over decoded values then FP32 rerank of the pool: the oracle runs
     Algorithm 1 on the decoded vectors with k = pool, then reranks in FP32."""

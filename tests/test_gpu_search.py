@@ -119,7 +119,7 @@ def test_parity_small_graphs(A, kind, metric, m, k, eps):
     assert_parity(got, ref, "parity %s m=%d k=%d eps=%g" % (kind, m, k, eps))
 
 
-@pytest.mark.parametrize("k", [128, 256, 300, 512])
+@pytest.mark.parametrize("k", [128, 256, 300, 512, 700, 1024])
 def test_parity_large_k(A, k):
     x, adj = graph(1500, 24, 30)
     q = queries_for("int", 56, 60, 24)
@@ -215,6 +215,23 @@ def test_parity_unpadded_adjacency(A):
         assert (u == v).all()
     ref = oracle.range_search(x, adj, q, [0], 10, 0.2, cap_L=max(256, 8 * 10))
     assert_parity(tuple(outs[0]), ref, "unpadded")
+
+
+def test_parity_exploration_k1000(A):
+    """The exploratory task at k = 1000 (Sec. 6.7): the query vertex seeds the
+    search and is never returned; 1,000 results per query with the library's
+    default capacity of S (4,096 at this k) on both sides."""
+    x, adj = graph(1500, 100, 30, "unit", oracle.IP)
+    qids = synth.rng(74).choice(1500, size=40, replace=False).astype(np.int32)
+    say("exploration k=1000")
+    store = A.VectorStore(dev(x), "f32", oracle.IP)
+    g = A.DeviceGraph(dev(adj))
+    ids, ds, st = A.search_indexed(store, g, dev(qids), 1000, 0.1)
+    torch.cuda.synchronize()
+    got = (ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy())
+    assert not (got[0] == qids[:, None]).any()
+    ref = oracle.range_search_indexed(x, adj, qids, 1000, 0.1, oracle.IP, cap_L=4096)
+    assert_parity(got, ref, "exploration k=1000")
 
 
 def test_parity_indexed(A):
