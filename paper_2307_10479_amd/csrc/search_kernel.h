@@ -380,39 +380,43 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t id, int shift) {
     return ((uint32_t)id * 0x9E3779B1u) >> shift;
 }
 
+// Position, within an aligned group of four slots, of the first slot at or
+// after position j0 that holds `id` or is empty: 0..3 for an empty slot, 4..7
+// for the slot holding id, -1 if neither occurs. Plain selects, no branches.
+__device__ __forceinline__ int group_scan(const int4 &q, uint32_t j0, int32_t id) {
+    int c = -1;
+    c = (q.w == id || q.w == -1) ? (q.w == id ? 7 : 3) : c;
+    c = (j0 <= 2u && (q.z == id || q.z == -1)) ? (q.z == id ? 6 : 2) : c;
+    c = (j0 <= 1u && (q.y == id || q.y == -1)) ? (q.y == id ? 5 : 1) : c;
+    c = (j0 == 0u && (q.x == id || q.x == -1)) ? (q.x == id ? 4 : 0) : c;
+    return c;
+}
+
 // Linear-probing insert of `id` into `tab` (power-of-two size msk + 1, a
 // multiple of 4) starting at slot s. Slots are read four at a time (one
-// 16-byte load covers the next probe positions of the aligned group); an
-// empty slot is claimed with compare-and-swap, so a slot only ever goes from
-// -1 to an id. The probe order is the plain linear order s, s+1, ..., so the
-// set is the same as with one-slot probing. A stale read can only show -1
-// where an id already is: the CAS then returns that id and the probe moves on.
+// 16-byte load covers the next probe positions of the aligned group); the
+// first empty slot in probe order is claimed with compare-and-swap, so a slot
+// only ever goes from -1 to an id. The probe order is the plain linear order
+// s, s+1, ..., so the set is the same as with one-slot probing. A stale read
+// can only show -1 where an id already is: the CAS then returns that id (done)
+// or another one (the probe goes on after that slot).
 // Returns true where id was not in the set.
 __device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
-    bool isnew = false, done = false;
-    while (!done) {
+    for (;;) {
         const uint32_t g = s & ~3u;
         const int4 q4 = *reinterpret_cast<const int4 *>(tab + g);
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            if (!done && g + (uint32_t)j >= s) {
-                const int32_t v = j == 0 ? q4.x : (j == 1 ? q4.y : (j == 2 ? q4.z : q4.w));
-                if (v == id) {
-                    done = true;
-                } else if (v == -1) {
-                    const int32_t old = atomicCAS(&tab[g + j], -1, id);
-                    if (old == -1) {
-                        isnew = true;
-                        done = true;
-                    } else if (old == id) {
-                        done = true;
-                    }
-                }
-            }
+        const int c = group_scan(q4, s & 3u, id);
+        if (c >= 4) return false;
+        if (c < 0) {
+            s = (g + 4u) & msk;
+            continue;
         }
-        s = (g + 4u) & msk;
+        const uint32_t t = g + (uint32_t)c;
+        const int32_t old = atomicCAS(&tab[t], -1, id);
+        if (old == -1) return true;
+        if (old == id) return false;
+        s = (t + 1u) & msk;
     }
-    return isnew;
 }
 
 // Linear-probing insert by compare-and-swap on each probed slot (one round
@@ -444,21 +448,10 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
         if (pending) {
             const uint32_t g = s & ~3u;
             const int4 q4 = *reinterpret_cast<const int4 *>(tab + g);
-            bool done = false;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                if (!done && g + (uint32_t)j >= s) {
-                    const int32_t v = j == 0 ? q4.x : (j == 1 ? q4.y : (j == 2 ? q4.z : q4.w));
-                    if (v == id) {
-                        done = true;
-                        pending = false;
-                    } else if (v == -1) {
-                        done = true;
-                        target = g + (uint32_t)j;
-                    }
-                }
-            }
-            if (!done) s = (g + 4u) & msk;
+            const int c = group_scan(q4, s & 3u, id);
+            if (c >= 4) pending = false;
+            else if (c >= 0) target = g + (uint32_t)c;
+            else s = (g + 4u) & msk;
         }
         // claims: lowest lane per slot wins; a loser holding the winner's id
         // (the same id twice in one adjacency row) finds it present
