@@ -327,6 +327,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     uint64_t *mbuf = stg + 2 * WAVE;
     uint32_t *hist = reinterpret_cast<uint32_t *>(mbuf + RREG * WAVE);
     uint16_t *hbuf = reinterpret_cast<uint16_t *>(hist + WAVE);
+    // candidate hand-out area of the distance batches: the staging keys, which
+    // only live inside one S operation
+    int32_t *xb = reinterpret_cast<int32_t *>(stg);
 
     Visited V;
     V.htab = htab;
@@ -463,7 +466,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             int cnt = __popcll(nm);
             V.count += cnt;
             evals += cnt;
-            float cd = batch_dist<DT, METRIC, QCH>(P, qv, seed_l, nm, nch, mask_tail);
+            float cd = batch_dist<DT, METRIC, QCH>(P, qv, seed_l, nm, nch, mask_tail, xb);
             uint64_t ck = isnew ? make_key(cd, seed_l) : KEY_MAX;
             if (cnt > 0) dseed = key_dist(wave_min_u64(ck));
             int na;
@@ -590,7 +593,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             n_acc_s = 0;
             n_acc_r = 0;
             if (cnt == 0) continue;
-            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail);
+            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb);
             const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
 
             // the closest new candidate is the likely next pop: load its row now
@@ -638,7 +641,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 if (cntr > 0) {
                     const uint64_t pm2 = cntr == WAVE ? ~0ull : ((1ull << cntr) - 1ull);
                     const int32_t id = lane < cntr ? key_id(R[r2]) : 0;
-                    float dd = batch_dist<DT, METRIC, QCH, true>(P, qv, id, pm2, nch, mask_tail);
+                    float dd = batch_dist<DT, METRIC, QCH, true>(P, qv, id, pm2, nch, mask_tail, xb);
                     NK[r2] = lane < cntr ? make_key(dd, id) : KEY_MAX;
                 }
             }

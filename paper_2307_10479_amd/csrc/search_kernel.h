@@ -364,6 +364,89 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
     return batch_dist_g<DT, METRIC, QCH, F32ROWS, GM>(P, qv, cand, mask, nch, mask_tail);
 }
 
+// The same distances with the candidates handed out through LDS: each
+// candidate lane writes its id at its rank among the set lanes (xb[0..64)),
+// half-wave h of group g in a round reads rank 2g + h, and the two sums of a
+// group go back through xb[64..128) to the candidates' own lanes. This takes
+// the place of the per-group bit scans and cross-lane reads of batch_dist_g.
+// xb: 128 words of LDS owned by the calling wave.
+template <int DT, int METRIC, int QCH, bool F32ROWS, int G>
+__device__ __forceinline__ float batch_dist_xg(const SearchParams &P, const float4 (&qv)[QCH],
+                                               int32_t cand, uint64_t mask, int nch, bool mask_tail,
+                                               int32_t *xb) {
+    constexpr int DL = F32ROWS ? DT_F32 : DT;
+    using Raw = typename RawChunk<DL>::T;
+    const int lane = lane_id();
+    const int half = lane >> 5, p = lane & 31;
+    const int cnt = __popcll(mask);
+    const bool mine = (mask >> lane) & 1ull;
+    const int rk = prefix_in(mask);
+    float *xr = reinterpret_cast<float *>(xb + WAVE);
+    if (mine) xb[rk] = cand;
+    wave_sync();
+    for (int base = 0; base < cnt; base += 2 * G) {
+        Raw raw[G][QCH];
+        float sc[G];
+        bool ok[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int j = base + 2 * g + half;
+            ok[g] = j < cnt;
+            const int32_t id = ok[g] ? xb[j & (WAVE - 1)] : 0;
+            sc[g] = 1.0f;
+            if constexpr (DL == DT_FP8) sc[g] = P.scale[id];
+#pragma unroll
+            for (int c = 0; c < QCH; ++c) {
+                const int ch = p + 32 * c;
+                const int che = ch < nch ? ch : 0;
+                if constexpr (F32ROWS) {
+                    raw[g][c] = reinterpret_cast<const float4 *>(P.f32 + (int64_t)id * P.f32_stride)[che];
+                } else {
+                    raw[g][c] = load_raw<DL>(P, id, che);
+                }
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            if (base + 2 * g >= cnt) break;
+            float acc = 0.0f;
+#pragma unroll
+            for (int c = 0; c < QCH; ++c) {
+                const int ch = p + 32 * c;
+                float4 x = decode_raw<DL>(raw[g][c], sc[g]);
+                if (!ok[g] || ch >= nch) x = make_float4(0.f, 0.f, 0.f, 0.f);
+                if (mask_tail) {
+                    const int b4 = 4 * ch;
+                    if (b4 + 0 >= P.dim) x.x = 0.f;
+                    if (b4 + 1 >= P.dim) x.y = 0.f;
+                    if (b4 + 2 >= P.dim) x.z = 0.f;
+                    if (b4 + 3 >= P.dim) x.w = 0.f;
+                }
+                acc = acc_chunk<METRIC>(acc, x, qv[c]);
+            }
+            acc = half_reduce(acc);  // the half's sum in its lane 0
+            if (METRIC == DEG_METRIC_IP) acc = __fsub_rn(1.0f, acc);
+            if (p == 0 && ok[g]) xr[base + 2 * g + half] = acc;
+        }
+    }
+    wave_sync();
+    const float res = mine ? xr[rk] : 0.0f;
+    wave_sync();
+    return res;
+}
+
+template <int DT, int METRIC, int QCH, bool F32ROWS = false>
+__device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
+                                            int32_t cand, uint64_t mask, int nch, bool mask_tail,
+                                            int32_t *xb) {
+    constexpr int GM = dist_rounds_max<F32ROWS ? DT_F32 : DT, QCH>();
+    const int cnt = __popcll(mask);
+    if (GM >= 2 && cnt <= 2) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 1>(P, qv, cand, mask, nch, mask_tail, xb);
+    if (GM >= 4 && cnt <= 4) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 2>(P, qv, cand, mask, nch, mask_tail, xb);
+    if (GM >= 8 && cnt <= 8) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 4>(P, qv, cand, mask, nch, mask_tail, xb);
+    return batch_dist_xg<DT, METRIC, QCH, F32ROWS, GM>(P, qv, cand, mask, nch, mask_tail, xb);
+}
+
 // ---------------------------------------------------------------- visited set
 // Visited set C of one query. It starts in an LDS hash table; when that
 // fills, every id moves to the query's table in the workspace, which from
