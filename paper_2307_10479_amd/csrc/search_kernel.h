@@ -475,26 +475,40 @@ __device__ __forceinline__ int group_scan(const int4 &q, uint32_t j0, int32_t id
     return c;
 }
 
+// The same over eight slots read as two groups of four (the aligned group
+// holding position j0, then the next group, whose positions all count):
+// 0..7 for the first empty slot, 8..15 for the slot holding id (offsets from
+// the first group's start), -1 if neither occurs.
+__device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_t j0, int32_t id) {
+    const int c0 = group_scan(a, j0, id);
+    const int c1 = group_scan(b, 0u, id);
+    const int r1 = c1 < 0 ? -1 : (c1 >= 4 ? c1 + 8 : c1 + 4);  // 4..7 empty, 12..15 present
+    const int r0 = c0 >= 4 ? c0 + 4 : c0;                        // 0..3 empty, 8..11 present
+    return c0 >= 0 ? r0 : r1;
+}
+
 // Linear-probing insert of `id` into `tab` (power-of-two size msk + 1, a
-// multiple of 4) starting at slot s. Slots are read four at a time (one
-// 16-byte load covers the next probe positions of the aligned group); the
-// first empty slot in probe order is claimed with compare-and-swap, so a slot
-// only ever goes from -1 to an id. The probe order is the plain linear order
-// s, s+1, ..., so the set is the same as with one-slot probing. A stale read
-// can only show -1 where an id already is: the CAS then returns that id (done)
-// or another one (the probe goes on after that slot).
+// multiple of 8) starting at slot s. Eight slots are read per round (the
+// aligned group of four holding s and the next group, two 16-byte loads), so
+// that a probe rarely needs a second round; the first empty slot in probe
+// order is claimed with compare-and-swap, so a slot only ever goes from -1 to
+// an id. The probe order is the plain linear order s, s+1, ..., so the set is
+// the same as with one-slot probing. A stale read can only show -1 where an id
+// already is: the CAS then returns that id (done) or another one (the probe
+// goes on after that slot).
 // Returns true where id was not in the set.
 __device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
     for (;;) {
         const uint32_t g = s & ~3u;
-        const int4 q4 = *reinterpret_cast<const int4 *>(tab + g);
-        const int c = group_scan(q4, s & 3u, id);
-        if (c >= 4) return false;
+        const int4 a = *reinterpret_cast<const int4 *>(tab + g);
+        const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
+        const int c = group_scan8(a, b, s & 3u, id);
+        if (c >= 8) return false;
         if (c < 0) {
-            s = (g + 4u) & msk;
+            s = (g + 8u) & msk;
             continue;
         }
-        const uint32_t t = g + (uint32_t)c;
+        const uint32_t t = (g + (uint32_t)c) & msk;
         const int32_t old = atomicCAS(&tab[t], -1, id);
         if (old == -1) return true;
         if (old == id) return false;
@@ -514,8 +528,8 @@ __device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t 
 }
 
 // Insert into the query's workspace table, which only this wave touches. Each
-// lane reads its next group of four slots and stops at its id (present) or at
-// the first empty slot (new); lanes aiming at the same empty slot are told
+// lane reads its next eight slots and stops at its id (present) or at the
+// first empty slot (new); lanes aiming at the same empty slot are told
 // apart in registers (the lowest lane takes it, the others probe on), and the
 // winners claim their slots with plain stores: one memory round trip for the
 // usual hop, none waiting for a store. The workgroup-scope fence at the top
@@ -530,11 +544,12 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
         uint32_t target = 0xFFFFFFFFu;
         if (pending) {
             const uint32_t g = s & ~3u;
-            const int4 q4 = *reinterpret_cast<const int4 *>(tab + g);
-            const int c = group_scan(q4, s & 3u, id);
-            if (c >= 4) pending = false;
-            else if (c >= 0) target = g + (uint32_t)c;
-            else s = (g + 4u) & msk;
+            const int4 a = *reinterpret_cast<const int4 *>(tab + g);
+            const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
+            const int c = group_scan8(a, b, s & 3u, id);
+            if (c >= 8) pending = false;
+            else if (c >= 0) target = (g + (uint32_t)c) & msk;
+            else s = (g + 8u) & msk;
         }
         // claims: lowest lane per slot wins; a loser holding the winner's id
         // (the same id twice in one adjacency row) finds it present
