@@ -573,7 +573,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             if (lane < deg)
                 nb = s == run_v ? run_nb : (s == spec_v ? spec_nb : P.adj[(int64_t)s * P.astride + lane]);
             run_v = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
-            run_nb = (run_v >= 0 && lane < deg) ? P.adj[(int64_t)run_v * P.astride + lane] : -1;
+            // (its lanes below the degree are read only when the next pop is run_v)
+            const int32_t *pf = P.adj + ((run_v >= 0 && lane < deg) ? (int64_t)run_v * P.astride + lane : 0);
             const bool bad = lane < deg && (nb < 0 || (int64_t)nb >= P.n);
             if (bad) nb = -1;
             if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
@@ -585,7 +586,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 flags |= DEG_FLAG_HASH_FULL;
                 break;
             }
-            const bool isnew = visit_insert(V, nb, nb >= 0);
+            // the runner-up's row is requested inside the check, after its table reads
+            const bool isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
             const uint64_t nm = ballot(isnew);
             const int cnt = __popcll(nm);
             V.count += cnt;

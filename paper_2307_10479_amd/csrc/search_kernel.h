@@ -535,17 +535,32 @@ __device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t 
 // usual hop, none waiting for a store. The workgroup-scope fence at the top
 // of each round waits for this wave's earlier stores, after which every lane
 // of the wave reads them.
+// With PF, one prefetch word per lane (pfv = *pf; pf must be a valid address
+// in every lane) is loaded right after each round's table reads: vector loads
+// complete in issue order, so the wait on those reads does not include it (it
+// is issued in every round so that all paths into the scan wait alike). pfv is
+// not consumed here.
+template <bool PF>
 __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
-                                              bool act) {
+                                              bool act, const int32_t *pf, int32_t &pfv) {
     const int lane = lane_id();
     bool isnew = false, pending = act;
-    while (ballot(pending) != 0) {
+    if (ballot(pending) == 0) {
+        if (PF) pfv = *pf;
+        return false;
+    }
+    for (;;) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+        // every lane reads (a finished lane its last group, a valid slot)
+        const uint32_t g = s & ~3u;
+        const int4 a = *reinterpret_cast<const int4 *>(tab + g);
+        const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
+        if (PF) {
+            __asm__ volatile("" ::: "memory");  // keeps the prefetch behind the table reads
+            pfv = *pf;
+        }
         uint32_t target = 0xFFFFFFFFu;
         if (pending) {
-            const uint32_t g = s & ~3u;
-            const int4 a = *reinterpret_cast<const int4 *>(tab + g);
-            const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
             const int c = group_scan8(a, b, s & 3u, id);
             if (c >= 8) pending = false;
             else if (c >= 0) target = (g + (uint32_t)c) & msk;
@@ -573,18 +588,28 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
         } else if (target != 0xFFFFFFFFu) {
             s = (target + 1u) & msk;  // the slot is taken by a lower lane: probe on
         }
+        if (ballot(pending) == 0) break;
     }
     return isnew;
 }
 
-// Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the set.
-__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
+// Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the
+// set. With PF also loads pfv = *pf (pf valid in every lane), issued after the
+// workspace-table reads.
+template <bool PF>
+__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act, const int32_t *pf,
+                                             int32_t &pfv) {
     if (!V.spilled) {
+        if (PF) pfv = *pf;
         bool isnew = false;
         if (act) isnew = probe_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), id);
         return isnew;
     }
-    return global_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id, act);
+    return global_insert<PF>(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id, act, pf, pfv);
+}
+__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
+    int32_t unused = 0;
+    return visit_insert<false>(V, id, act, nullptr, unused);
 }
 
 // Moves the LDS table to the workspace table (cleared first).
