@@ -579,6 +579,25 @@ def main(argv=None):
         log("P  sweep (L, eps, recall, ms, evals):", fmt(rowsP))
         log("B  sweep (L, eps, recall, ms, evals):", fmt(rowsB))
 
+        # ---- re-tune the launch at the settings that reach the recall target (on
+        # training queries: the launch shape changes no result, only the time),
+        # then keep the fastest of them
+        ntune = min(train.shape[0], nq)
+        Tt = dev(train[:ntune])
+        tts = torch.full((ntune, 1), seed, dtype=torch.int32, device="cuda")
+        for name, store, op in (("P", s32, opP), ("B", s16, opB)):
+            best, _table = tune.tune(store, G, Tt, tts, k, op["eps"], save=False, queue_cap=op["L"])
+            tuned[name] = dict(hash_slots=best["hash_slots"], waves_per_cu=best["waves_per_cu"])
+        log("re-tuned at the operating points:", tuned)
+        del Tt, tts
+        okP = [measure("P", x["eps"], None, x["L"]) for x in rowsP if x["recall"] >= a.recall]
+        okB = [measure("B", x["eps"], None, x["L"]) for x in rowsB if x["recall"] >= a.recall]
+        if okP:
+            opP = min(okP, key=lambda x: x["ms"])
+        if okB:
+            opB = min(okB, key=lambda x: x["ms"])
+        log("operating points after re-tuning: P", fmt([opP]), "B", fmt([opB]))
+
         # ---- learned stop: traces, training, calibration (all on the GPU)
         t1 = time.time()
         ntr = train.shape[0]

@@ -19,7 +19,7 @@ import torch
 from . import api
 
 CACHE = Path(os.environ.get("DEG_TUNE_CACHE", Path.home() / ".cache" / "deg_tune.json"))
-HASH_SLOTS = (1024, 2048, 4096, 8192)
+HASH_SLOTS = (256, 512, 1024, 2048, 4096, 8192)
 WAVES_PER_CU = (0, 4, 6, 8, 12, 16)
 
 
