@@ -54,7 +54,7 @@ def test_argument_validation_rejects_before_any_gpu_call(L):
     bad.append(call(v, g))                          # degree below 4
     v, g = _vec_graph(api)
     bad.append(call(v, g, k=0))                     # k < 1
-    bad.append(call(v, g, k=513))                   # k above the supported maximum
+    bad.append(call(v, g, k=1025))                  # k above the supported maximum (1024)
     bad.append(call(v, g, eps=-0.5))                # negative range factor
     bad.append(call(v, g, eps=float("nan")))
     bad.append(call(v, g, ns=0))                    # no seed
