@@ -116,8 +116,9 @@ typedef struct {
                            when |S| > L + 64 the entries beyond the threshold r(1+eps) are
                            dropped, then if still |S| > L + 64 only the L smallest stay
                            (DEG_FLAG_QUEUE_OVERFLOW); 0 = default min(4096, max(256, 8 k_pool)) */
-    int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = tuned or
-                           default. The set moves to a workspace table at 3/4 load. */
+    int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = the tuned
+                           value if one is registered, else 512. The set moves to a
+                           workspace table at 3/4 load. */
     int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
                            from f32_data when k_pool > k or dtype != DEG_F32; 0 = k */
     int32_t rerank;     /* 1 = always rerank the pool in FP32, 0 = only when needed */

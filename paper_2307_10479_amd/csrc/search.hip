@@ -82,7 +82,9 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     c.L = L;
     c.scap = ((L + 192 > kp ? L + 192 : kp) + 63) / 64 * 64;  // B (L + 64 + two pushes) / rerank buffer
     const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);
-    int H = (o && o->hash_slots) ? o->hash_slots : (t ? t->hash_slots : (kp <= 32 ? 2048 : 4096));
+    // untuned default: a small LDS table and more resident waves (the workspace
+    // table takes over at 3/4 load; measured best or near-best on every workload)
+    int H = (o && o->hash_slots) ? o->hash_slots : (t ? t->hash_slots : 512);
     c.H = H;
     c.hshift = 32 - ilog2(H);
     int Hg = 1 << 16;
