@@ -36,9 +36,8 @@ __device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float acc) {
 }
 
 // The weights lane j needs (row j of W1 and W2 as BF16 pairs, b1[j], b2[j],
-// w3[j], b3), kept in registers: 40 words and 4 floats per lane. A search
-// wave loads them once and evaluates the network at every checkpoint without
-// reading weights from memory.
+// w3[j], b3) in registers: 40 words and 4 floats per lane, read with ten
+// 16-byte loads and four 2-byte loads.
 struct MlpRegs {
     uint32_t w1[8];
     uint32_t w2[32];

@@ -345,11 +345,12 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     const int hlimit = (3 * P.H) / 4;
     const int glimit = (3 * P.Hg) / 4;
 
-    // stop model: weights and feature standardisation stay in registers for the whole launch
-    MlpRegs M{};
+    // stop model: the feature standardisation stays in registers for the whole
+    // launch; the weights (10.6 KB shared by every wave, so they stay in L2) are
+    // read at each checkpoint, which keeps 44 registers per lane free between
+    // checkpoints (more resident waves)
     float f_mean = 0.f, f_istd = 0.f;
     if (FEAT && P.stop_w != nullptr) {
-        M = mlp_load(P.stop_w);
         if (lane < NFEAT) {
             f_mean = P.stop_mean[lane];
             f_istd = P.stop_istd[lane];
@@ -499,6 +500,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 if (to_trace == 0) to_trace = P.trace_interval;
             }
             if (want_stop || want_trace) {
+                MlpRegs M{};
+                if (want_stop) M = mlp_load(P.stop_w);  // in flight while the features are formed
                 // lane i < 16 computes state feature i (raw); all inputs are wave-uniform
                 const int kq = min(k, rcnt);
                 const float d1 = rcnt > 0 ? key_dist(r_at<RREG>(R, 0)) : 0.f;
