@@ -375,6 +375,24 @@ def run_batch(a):
             res[mth]["top10_agreement_with_P"] = stop.agreement_flat(ids, plain_ids, kk, off)
         log("%-2s %.3f ms  %.0f QPS  recall@10 %.4f  hops %.1f evals %.1f  %.0f GB/s"
             % (mth, ms, res[mth]["qps"], r, hops / nq, evals / nq, res[mth]["gbs"]))
+    # ---- B with a rerank pool larger than k (one pool size for the whole launch):
+    # the BF16 traversal then reaches the neighbours its rounding would lose
+    for kp in (20, 50, 100):
+        ms, (ids, ds, st) = _timed_launch(torch, lambda: launch(s16, None, k_pool=kp), a.warmup,
+                                          a.steps)
+        stn = st.cpu().numpy()
+        evals = int(stn[:, 1].astype(np.int64).sum())
+        hops = int(stn[:, 0].astype(np.int64).sum())
+        pool = int(np.maximum(kk, kp).sum())
+        alg = evals * 2 * m + hops * 4 * d + nq * (4 * m + 16) + int(kk.sum()) * 8 + pool * 4 * m
+        r = recall(ids)
+        name_ = "B_pool%d" % kp
+        res[name_] = dict(ms=ms, qps=nq / (ms / 1e3), recall_at_10=r, hops=hops / nq,
+                          evals=evals / nq, alg_bytes=alg, gbs=alg / (ms / 1e3) / 1e9,
+                          top10_agreement_with_P=stop.agreement_flat(ids, plain_ids, kk, off))
+        log("B, pool %3d: %.3f ms  %.0f QPS  recall@10 %.4f  agreement with P %.4f  hops %.1f "
+            "evals %.1f" % (kp, ms, res[name_]["qps"], r, res[name_]["top10_agreement_with_P"],
+                            hops / nq, evals / nq))
     head = res["BL"]
     cpu = None
     if not a.no_cpu_baseline:
