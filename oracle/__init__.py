@@ -74,7 +74,10 @@ def _declare(L):
     L.or_dist64.argtypes = [P, P, I64, I32]
     L.or_range_search.restype = I32
     L.or_range_search.argtypes = [P, I64, I64, I64, I32, P, I32, I64, P, I64, I64, P, I32, P, P, P,
-                                  I32, F32, I64, I32, P, P, I64, P, I32]
+                                  P, P, I32, I32, F32, I64, I32, P, P, I64, I32, P, P, I64, P, I32]
+    L.or_mlp_logit_bf16.restype = F32
+    L.or_mlp_logit_bf16.argtypes = [P, P]
+    L.or_mlp_logits_bf16_rows.argtypes = [P, P, I64, P]
     L.or_rerank.restype = I32
     L.or_rerank.argtypes = [P, I64, I64, I32, P, P, I32, I32, P, P]
     L.or_knn64.restype = I32
@@ -153,14 +156,62 @@ def dist64(x, q, metric=L2) -> float:
 
 
 # ---------------------------------------------------------------- search
+class _OrStop(C.Structure):
+    _fields_ = [("w", C.c_void_p), ("mean", C.c_void_p), ("istd", C.c_void_p),
+                ("tau", C.c_float), ("tau_long", C.c_float), ("interval", C.c_int32),
+                ("long_hops", C.c_int32)]
+
+
+class StopModel:
+    """Learned-stop parameters for the oracle's search: BF16 weights (5313 uint16
+    bit patterns), the 16 feature means and inverse standard deviations, the
+    probability threshold tau (tau_long from hop long_hops on) and the
+    checkpoint interval."""
+
+    def __init__(self, w_bf16, mean, inv_std, tau, interval, tau_long=None, long_hops=0):
+        self.w = np.ascontiguousarray(w_bf16, np.uint16)
+        self.mean = _f32(mean)
+        self.istd = _f32(inv_std)
+        assert self.w.shape == (5313,) and self.mean.shape == (16,) and self.istd.shape == (16,)
+        self.tau, self.interval = float(tau), int(interval)
+        self.tau_long = float(tau if tau_long is None else tau_long)
+        self.long_hops = int(long_hops)
+
+    def c(self):
+        return _OrStop(self.w.ctypes.data, self.mean.ctypes.data, self.istd.ctypes.data,
+                       self.tau, self.tau_long, self.interval, self.long_hops)
+
+
+def _exclusion_csr(exclude, nq):
+    """Per-query exclusion lists as CSR arrays: `exclude` is an (nq,) id array
+    (one id per query, -1 = none) or a sequence of nq id lists."""
+    if exclude is None:
+        return None, None
+    if isinstance(exclude, np.ndarray) and exclude.ndim == 1 and exclude.dtype != object:
+        lists = [[int(v)] if v >= 0 else [] for v in exclude.tolist()]
+    else:
+        lists = [list(map(int, e)) for e in exclude]
+    assert len(lists) == nq
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum([len(e) for e in lists])
+    ids = np.array([v for e in lists for v in e] or [0], np.int32)
+    return off, ids
+
+
 def range_search(vec, adj, queries, seeds, k, eps, metric=L2, exclude=None, cap_L=0,
-                 order_mode=0, k_arr=None, eps_arr=None, out_k=None, nthreads=None):
+                 order_mode=0, k_arr=None, eps_arr=None, out_k=None, nthreads=None, k_pool=0,
+                 kind=None, stop: StopModel | None = None, trace_rows=0, trace_interval=0):
     """RangeSearch (Algorithm 1) for every query row.
 
     seeds: (nq, ns) int32 or (ns,) shared by all queries.
-    exclude: optional (nq,) ids kept out of the result (exploratory search).
+    exclude: optional per-query ids kept out of the result, (nq,) or a list of lists
+    (they still enter S and C).
+    k_pool: R holds max(k, k_pool) entries; out_k of them are returned.
+    kind: optional (nq,) 1 for exploratory queries (a stop feature).
+    stop: optional learned stop; trace_rows > 0 also returns the trace rows
+    (nq, trace_rows, 20).
     Returns ids (nq, out_k), dists (nq, out_k), stats (nq, 4) = hops, evals,
-    max live |S|, overflow.
+    max live |S|, flags (1 overflow, 16 learned stop) [, trace].
     """
     vec, queries, adj = _f32(vec), _f32(queries), _i32(adj)
     n, m = vec.shape
@@ -169,27 +220,37 @@ def range_search(vec, adj, queries, seeds, k, eps, metric=L2, exclude=None, cap_
     if seeds.ndim == 1:
         seeds = np.broadcast_to(seeds, (nq, seeds.shape[0]))
     seeds = np.ascontiguousarray(seeds, dtype=np.int32)
-    ex = None if exclude is None else _i32(exclude)
+    ex_off, ex_ids = _exclusion_csr(exclude, nq)
     ka = None if k_arr is None else _i32(k_arr)
     ea = None if eps_arr is None else _f32(eps_arr)
+    kd = None if kind is None else _i32(kind)
     ok = int(out_k or (int(ka.max()) if ka is not None else k))
     ids = np.empty((nq, ok), np.int32)
     ds = np.empty((nq, ok), np.float32)
     st = np.empty((nq, 4), np.int64)
+    sc = None if stop is None else stop.c()
+    tr = np.empty((nq, trace_rows, 20), np.float32) if trace_rows > 0 else None
     rc = lib().or_range_search(_p(vec), n, m, m, metric, _p(adj), adj.shape[1], adj.shape[1],
-                               _p(queries), nq, m, _p(seeds), seeds.shape[1], _p(ex), _p(ka),
-                               _p(ea), int(k), float(eps), int(cap_L), int(order_mode), _p(ids),
-                               _p(ds), ok, _p(st), int(nthreads or nthreads_default()))
+                               _p(queries), nq, m, _p(seeds), seeds.shape[1], _p(ex_off),
+                               _p(ex_ids), _p(ka), _p(ea), _p(kd), int(k), int(k_pool),
+                               float(eps), int(cap_L), int(order_mode),
+                               None if sc is None else C.byref(sc), _p(tr), int(trace_rows),
+                               int(trace_interval), _p(ids), _p(ds), ok, _p(st),
+                               int(nthreads or nthreads_default()))
     if rc:
         raise ValueError("or_range_search: invalid arguments")
-    return ids, ds, st
+    return (ids, ds, st) if tr is None else (ids, ds, st, tr)
 
 
-def range_search_indexed(vec, adj, qids, k, eps, metric=L2, query_vec=None, **kw):
-    """Exploratory search: seed = the query's own vertex, which is kept out of R."""
+def range_search_indexed(vec, adj, qids, k, eps, metric=L2, query_vec=None, exclude=None, **kw):
+    """Exploratory search: seed = the query's own vertex, which is kept out of R
+    (with `exclude`, a list of lists, further ids are kept out too)."""
     qids = _i32(qids)
     qv = _f32(vec if query_vec is None else query_vec)[qids]
-    return range_search(vec, adj, qv, qids[:, None], k, eps, metric, exclude=qids, **kw)
+    ex = [[int(v)] for v in qids.tolist()] if exclude is None else \
+        [[int(v)] + list(map(int, e)) for v, e in zip(qids.tolist(), exclude)]
+    kw.setdefault("kind", np.ones(len(qids), np.int32))
+    return range_search(vec, adj, qv, qids[:, None], k, eps, metric, exclude=ex, **kw)
 
 
 def rerank(vec, q, pool, k, metric=L2):
@@ -368,23 +429,14 @@ def adam_step(params, grad, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     lib().or_adam_step(_p(params), _p(g), _p(m), _p(v), params.shape[0], t, lr, b1, b2, eps)
 
 
-def mlp_logits_bf16(params, X):
-    """BF16 inference of the 16-64-64-1 network (logits, FP64 accumulation).
-
-    `params` are the BF16 weights as values (already representable); the
-    features X and the first hidden layer's ReLU outputs are rounded to BF16
-    (round-to-nearest-even) before they are multiplied; the second hidden
-    layer's outputs enter the final dot product unrounded."""
-    P = np.asarray(params, np.float64)
-    W1 = P[0:1024].reshape(64, 16)
-    b1 = P[1024:1088]
-    W2 = P[1088:5184].reshape(64, 64)
-    b2 = P[5184:5248]
-    w3 = P[5248:5312]
-    b3 = P[5312]
-    xb = bf16_decode(bf16_encode(np.asarray(X, np.float32))).astype(np.float64)
-    h1 = np.maximum(xb @ W1.T + b1, 0.0)
-    h1b = bf16_decode(bf16_encode(h1.astype(np.float32))).astype(np.float64)
-    h2 = np.maximum(h1b @ W2.T + b2, 0.0)
-    return h2 @ w3 + b3
-
+def mlp_logits_bf16(w_bf16, X):
+    """Logits of the stop network with BF16 weights (5313 uint16 bit patterns)
+    for rows of 16 standardised features: the FP32 definition of
+    or_mlp_logit_bf16 (BF16 inputs and first hidden layer, fused multiply-adds
+    in index order, a halving tree for the output layer)."""
+    w = np.ascontiguousarray(w_bf16, np.uint16)
+    assert w.shape == (5313,)
+    X = _f32(X)
+    out = np.empty(X.shape[0], np.float32)
+    lib().or_mlp_logits_bf16_rows(_p(w), _p(X), X.shape[0], _p(out))
+    return out

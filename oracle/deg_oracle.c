@@ -27,9 +27,9 @@
  *   - Algorithm 1 starts with the checked set C equal to the seeds (the
  *     printed C = {} would let a seed be checked twice).
  *   - The candidate set S may be bounded by a capacity L (0 = unbounded):
- *     after a hop, if S holds more than L + 64 entries, the dead ones
- *     (farther than the threshold) are dropped, and if still more than
- *     L + 64 remain, only the L smallest are kept.
+ *     a push into a full S evicts the (distance, id)-largest entry.
+ *   - The learned stop's state features, its BF16 inference (FP32 in a fixed
+ *     order) and its trace rows are defined next to range_search_core.
  *   - threshold = fl32(r * fl32(1 + eps)); r = inf gives inf.
  *   - Exploratory (indexed) search: excluded ids enter S and C but never R.
  *
@@ -262,7 +262,7 @@ typedef struct {
 } AdjView;
 
 typedef struct {
-    int64_t hops, evals, max_live, overflow;
+    int64_t hops, evals, max_live, overflow, flags;
 } SearchStats;
 
 static inline int is_excluded(int32_t id, const int32_t *ex, int nex) {
@@ -293,59 +293,188 @@ static uint64_t splitmix64(uint64_t *s) {
     return z ^ (z >> 31);
 }
 
-static int cmp_ent(const void *a, const void *b) {
-    Ent x = *(const Ent *)a, y = *(const Ent *)b;
-    return ent_less(x, y) ? -1 : (ent_less(y, x) ? 1 : 0);
+/* Layout of the stop network's parameters (16 -> 64 -> 64 -> 1). */
+#define MLP_IN_ 16
+#define MLP_H_ 64
+#define MOFF_W1 0
+#define MOFF_B1 (MOFF_W1 + MLP_H_ * MLP_IN_)
+#define MOFF_W2 (MOFF_B1 + MLP_H_)
+#define MOFF_B2 (MOFF_W2 + MLP_H_ * MLP_H_)
+#define MOFF_W3 (MOFF_B2 + MLP_H_)
+#define MOFF_B3 (MOFF_W3 + MLP_H_)
+
+/*
+ * Push into S with capacity L (a reading; the paper's S is unbounded): when S
+ * already holds L entries, the (distance, id)-largest of S and the new entry
+ * is evicted (the new one itself if it is the largest). `ev` receives the
+ * smallest distance evicted so far in the current hop, so that the caller can
+ * tell whether an entry within the end-of-hop threshold was lost.
+ */
+static void push_capped(Ctx *c, Ent e, int64_t L, float *ev) {
+    if (L <= 0 || c->hsize < L) {
+        heap_push(c, e);
+        return;
+    }
+    int64_t mx = 0;
+    for (int64_t i = 1; i < c->hsize; ++i)
+        if (ent_less(c->heap[mx], c->heap[i])) mx = i;
+    if (ent_less(e, c->heap[mx])) {
+        Ent out = heap_pop_at(c, mx);
+        if (out.d < *ev) *ev = out.d;
+        heap_push(c, e);
+    } else if (e.d < *ev) {
+        *ev = e.d;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* stop-predictor inference (BF16 weights, FP32 arithmetic in a fixed order) */
+/* ------------------------------------------------------------------------ */
+static inline float bf16_round(float x) {
+    uint32_t u;
+    memcpy(&u, &x, 4);
+    u = (u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u; /* nearest, ties to even (finite x) */
+    memcpy(&x, &u, 4);
+    return x;
+}
+
+static inline float bf16_value(uint16_t h) {
+    uint32_t u = (uint32_t)h << 16;
+    float x;
+    memcpy(&x, &u, 4);
+    return x;
 }
 
 /*
- * Capacity of S (a reading; the paper's S is unbounded): at the end of a hop,
- * if S holds more than L + 64 entries, the entries farther than the threshold
- * are removed (they can never be expanded); if more than L + 64 remain, only
- * the L smallest are kept. Returns 1 if live entries were dropped.
+ * Logit of the 16-64-64-1 stop network from BF16 weights w (layout W1[64][16],
+ * b1[64], W2[64][64], b2[64], w3[64], b3) and 16 standardised features fs.
+ * Definition, all in FP32 with round-to-nearest-even:
+ *   x_j  = bf16(fs_j)
+ *   h1_i = bf16(relu(b1_i (+) W1_i0 x_0 (+) ... (+) W1_i15 x_15))   fused
+ *          multiply-adds in increasing j (each product of two BF16 values is exact)
+ *   h2_i = relu(b2_i (+) W2_i0 h1_0 (+) ... (+) W2_i63 h1_63)          same
+ *   t_i  = fl(w3_i * h2_i); then the halving tree t_i = fl(t_i + t_{i+w}) for
+ *          w = 32, 16, 8, 4, 2, 1; logit = fl(t_0 + b3)
+ * relu(s) = s if s > 0, else +0.
  */
-static int apply_capacity(Ctx *c, int64_t L, float thr) {
-    if (c->hsize <= L + 64) return 0;
-    int64_t n = 0;
+float or_mlp_logit_bf16(const uint16_t *w, const float *fs) {
+    float x[MLP_IN_], h1[MLP_H_], t[MLP_H_];
+    for (int j = 0; j < MLP_IN_; ++j) x[j] = bf16_round(fs[j]);
+    for (int i = 0; i < MLP_H_; ++i) {
+        float s = bf16_value(w[MOFF_B1 + i]);
+        for (int j = 0; j < MLP_IN_; ++j) s = fmaf(bf16_value(w[MOFF_W1 + i * MLP_IN_ + j]), x[j], s);
+        h1[i] = bf16_round(s > 0.0f ? s : 0.0f);
+    }
+    for (int i = 0; i < MLP_H_; ++i) {
+        float s = bf16_value(w[MOFF_B2 + i]);
+        for (int j = 0; j < MLP_H_; ++j) s = fmaf(bf16_value(w[MOFF_W2 + i * MLP_H_ + j]), h1[j], s);
+        float h2 = s > 0.0f ? s : 0.0f;
+        t[i] = bf16_value(w[MOFF_W3 + i]) * h2;
+    }
+    for (int wd = MLP_H_ / 2; wd >= 1; wd /= 2)
+        for (int i = 0; i < wd; ++i) t[i] = t[i] + t[i + wd];
+    return t[0] + bf16_value(w[MOFF_B3]);
+}
+
+/* Logits of B rows (B x 16 standardised features). */
+void or_mlp_logits_bf16_rows(const uint16_t *w, const float *X, int64_t B, float *out) {
+    for (int64_t b = 0; b < B; ++b) out[b] = or_mlp_logit_bf16(w, X + b * MLP_IN_);
+}
+
+/* Per-search options beyond Algorithm 1's own inputs. */
+typedef struct {
+    int64_t cap_L;      /* capacity of S, 0 = unbounded */
+    int order_mode;     /* 0 row order, 1 reversed, 2 shuffled (the result must not depend on it) */
+    uint64_t order_seed;
+    int want_live;      /* report the largest number of live S entries */
+    /* state features (learned stop, trace rows) */
+    int32_t k_user;     /* the caller's k (R itself holds the pool of size k) */
+    int32_t kind;       /* 0 vector query, 1 exploratory */
+    const uint16_t *stop_w; /* NULL = plain rule only */
+    const float *stop_mean, *stop_istd;
+    float stop_z, stop_z_long; /* logit thresholds */
+    int32_t stop_interval, stop_long_hops;
+    float *trace;       /* NULL = no trace rows; else trace_rows rows of OR_TRACE_W floats */
+    int64_t trace_rows;
+    int32_t trace_interval;
+} SearchOpts;
+
+#define OR_NFEAT 16
+#define OR_TRACE_W 20
+#define OR_FLAG_QUEUE_OVERFLOW 1
+#define OR_FLAG_LEARNED_STOP 16
+
+/*
+ * The 16 search-state features of the stop predictor at a checkpoint (after
+ * the pop of hop h passed the threshold test, before its row is expanded).
+ * Every quantity is a function of Algorithm 1's state, so any exact
+ * implementation computes the same values; all arithmetic is FP32 with
+ * correctly rounded division and square root. With kq = min(k, |R|), d1 and
+ * dk the distances of R's first and kq-th entries:
+ *   0 sqrt(h)                        1 sqrt(evaluations)
+ *   2 d1 / dk                        3 d1 / (smallest seed distance)
+ *   4 r / (r at the previous checkpoint)
+ *   5 sqrt(hops since the first min(pool, 10) entries of R last changed)
+ *   6 sqrt(hops since R's first entry last changed)
+ *   7 (new candidates of the last expanded row within the end-of-row range r(1+eps)) / d
+ *   8 (new candidates of the last expanded row that are in R after it) / d
+ *   9 min(64, entries of S that precede R's kq-th entry) / 64
+ *  10 min(4, popped distance / dk)    11 min(eps, 4)
+ *  12 sqrt(k)                        13 1 for an exploratory query, else 0
+ *  14 sqrt(hops since r last changed) 15 constant 1
+ * A ratio whose divisor is zero or not finite (or whose dividend is not) is 1.
+ */
+typedef struct {
+    int64_t hops, evals;
+    float dseed, rprev;
+    int64_t last_top, last_d1, last_r;
+    int32_t n_s, n_r;
+} FeatState;
+
+static void state_features(const Ctx *c, const FeatState *F, int64_t rsize, float r, float ds,
+                           float eps, const SearchOpts *o, int32_t d, float *f) {
+    int64_t kq = o->k_user < rsize ? o->k_user : rsize;
+    float d1 = rsize > 0 ? c->R[0].d : 0.0f;
+    float dk = kq > 0 ? c->R[kq - 1].d : 0.0f;
+    int fin_k = kq > 0 && dk > 0.0f;
+    int64_t closer = 0;
     for (int64_t i = 0; i < c->hsize; ++i)
-        if (c->heap[i].d <= thr) c->heap[n++] = c->heap[i];
-    int dropped = 0;
-    if (n > L + 64) {
-        qsort(c->heap, (size_t)n, sizeof(Ent), cmp_ent);
-        n = L;
-        dropped = 1;
-    }
-    c->hsize = n;
-    for (int64_t i = n / 2 - 1; i >= 0; --i) { /* restore the heap: sift down, bottom up */
-        int64_t j = i;
-        for (;;) {
-            int64_t l = 2 * j + 1, rr = l + 1, b = j;
-            if (l < n && ent_less(c->heap[l], c->heap[b])) b = l;
-            if (rr < n && ent_less(c->heap[rr], c->heap[b])) b = rr;
-            if (b == j) break;
-            Ent t = c->heap[j];
-            c->heap[j] = c->heap[b];
-            c->heap[b] = t;
-            j = b;
-        }
-    }
-    return dropped;
+        if (kq == 0 || ent_less(c->heap[i], c->R[kq - 1])) closer++;
+    if (closer > 64) closer = 64;
+    f[0] = sqrtf((float)F->hops);
+    f[1] = sqrtf((float)F->evals);
+    f[2] = fin_k ? d1 / dk : 1.0f;
+    f[3] = (rsize > 0 && F->dseed > 0.0f && isfinite(F->dseed)) ? d1 / F->dseed : 1.0f;
+    f[4] = (isfinite(r) && isfinite(F->rprev) && F->rprev > 0.0f) ? r / F->rprev : 1.0f;
+    f[5] = sqrtf((float)(F->hops - F->last_top));
+    f[6] = sqrtf((float)(F->hops - F->last_d1));
+    f[7] = (float)F->n_s / (float)d;
+    f[8] = (float)F->n_r / (float)d;
+    f[9] = (float)closer / 64.0f;
+    f[10] = fin_k ? fminf(4.0f, ds / dk) : 1.0f;
+    f[11] = fminf(eps, 4.0f);
+    f[12] = sqrtf((float)o->k_user);
+    f[13] = (float)o->kind;
+    f[14] = sqrtf((float)(F->hops - F->last_r));
+    f[15] = 1.0f;
 }
 
 /*
  * RangeSearch (Algorithm 1) for one query.
- *   seeds/ns     : seed vertices (distinct)
- *   ex/nex       : ids never placed in R (exploratory search excludes the query vertex)
- *   cap_L        : capacity of S (0 = unbounded), applied at the end of each hop
- *   order_mode   : 0 = neighbours in row order, 1 = reversed, 2 = shuffled (seeded);
- *                  the result must not depend on it
- *   want_live    : compute the largest number of live S entries (dist <= threshold)
- * Output R sorted by (dist, id), *rsize entries.
+ *   seeds/ns : seed vertices (distinct)
+ *   ex/nex   : ids never placed in R (exploratory search excludes the query vertex
+ *              and any vertices already shown); they still enter S and C
+ *   k        : size of R (the traversal pool)
+ *   o        : capacity, row order, features / learned stop / trace rows
+ * Output R sorted by (dist, id), returned size; st gets the counters and flags.
+ * Capacity: S keeps at most L entries, a push into a full S evicting the
+ * (distance, id)-largest. The overflow flag is set when an evicted entry lies
+ * within the threshold r(1+eps) at the end of its hop (a live entry was lost;
+ * whether that happens does not depend on the order of a row's neighbours).
  */
 static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, const float *q,
                                  const int32_t *seeds, int ns, const int32_t *ex, int nex,
-                                 int32_t k, float eps, int64_t cap_L, int order_mode,
-                                 uint64_t order_seed, int want_live, SearchStats *st) {
+                                 int32_t k, float eps, const SearchOpts *o, SearchStats *st) {
     if (c->rcap < (int64_t)k + 1) {
         c->rcap = (int64_t)k + 1;
         c->R = (Ent *)realloc(c->R, sizeof(Ent) * c->rcap);
@@ -360,24 +489,75 @@ static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, con
     int64_t rsize = 0;
     float r = INFINITY;
     float onep = 1.0f + eps; /* fl32(1 + eps) */
-    SearchStats s = {0, 0, 0, 0};
-    uint64_t rs = order_seed;
+    SearchStats s = {0, 0, 0, 0, 0};
+    uint64_t rs = o->order_seed;
+    const int64_t L = o->cap_L;
+    const int feat = o->stop_w != NULL || o->trace != NULL;
+    const int t10 = k < 10 ? k : 10;
+    FeatState F = {0, 0, INFINITY, INFINITY, 0, 0, 0, 0, 0};
+    int64_t nrow = 0;
+    int32_t to_stop = o->stop_interval, to_trace = o->trace_interval;
 
     /* C <- seeds; every seed is evaluated once, enters S, and enters R unless excluded */
+    float ev = INFINITY;
     for (int i = 0; i < ns; ++i) c->stamp[seeds[i]] = c->epoch;
     for (int i = 0; i < ns; ++i) {
         int32_t t = seeds[i];
         Ent e = {or_dist32(V->vec + (int64_t)t * V->vs, q, V->m, V->metric), t};
         s.evals++;
-        heap_push(c, e);
+        if (e.d < F.dseed) F.dseed = e.d;
+        push_capped(c, e, L, &ev);
         if (!is_excluded(t, ex, nex)) insert_R(c, &rsize, k, e, &r);
     }
-    if (cap_L > 0 && apply_capacity(c, cap_L, thr_of(r, onep))) s.overflow = 1;
+    if (isfinite(ev) && ev <= thr_of(r, onep)) s.overflow = 1;
 
     while (c->hsize > 0) {
         Ent sv = heap_pop_at(c, 0); /* argmin of S */
         if (sv.d > thr_of(r, onep)) break; /* too far away: return R */
         s.hops++;
+
+        if (feat) { /* checkpoints of the learned stop and of the trace rows */
+            int want_stop = 0, want_trace = 0;
+            if (o->stop_w) {
+                if (--to_stop == 0) {
+                    want_stop = 1;
+                    to_stop = o->stop_interval;
+                }
+            }
+            if (o->trace) {
+                if (--to_trace == 0) {
+                    want_trace = nrow < o->trace_rows;
+                    to_trace = o->trace_interval;
+                }
+            }
+            if (want_stop || want_trace) {
+                float f[OR_NFEAT];
+                F.hops = s.hops;
+                F.evals = s.evals;
+                state_features(c, &F, rsize, r, sv.d, eps, o, G->d, f);
+                F.rprev = r;
+                if (want_trace) {
+                    float *row = o->trace + nrow * OR_TRACE_W;
+                    for (int i = 0; i < OR_NFEAT; ++i) row[i] = f[i];
+                    row[17] = 0.0f; /* query index: set by the caller */
+                    row[18] = (float)s.hops;
+                    row[19] = 0.0f;
+                    nrow++;
+                }
+                if (want_stop) {
+                    float fs[OR_NFEAT];
+                    for (int i = 0; i < OR_NFEAT; ++i)
+                        fs[i] = (f[i] - o->stop_mean[i]) * o->stop_istd[i];
+                    float z = or_mlp_logit_bf16(o->stop_w, fs);
+                    float zt = s.hops >= o->stop_long_hops ? o->stop_z_long : o->stop_z;
+                    if (z >= zt) {
+                        s.flags |= OR_FLAG_LEARNED_STOP;
+                        break;
+                    }
+                }
+            }
+        }
+
         /* N <- N(G,s) \ C ; C <- C u N */
         const int32_t *row = G->adj + (int64_t)sv.id * G->stride;
         int32_t deg = G->cnt ? G->cnt[sv.id] : G->d;
@@ -389,13 +569,13 @@ static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, con
                 c->nbuf[nn++] = nb;
             }
         }
-        if (order_mode == 1) {
+        if (o->order_mode == 1) {
             for (int a = 0, b = nn - 1; a < b; ++a, --b) {
                 int32_t t = c->nbuf[a];
                 c->nbuf[a] = c->nbuf[b];
                 c->nbuf[b] = t;
             }
-        } else if (order_mode == 2) {
+        } else if (o->order_mode == 2) {
             for (int a = nn - 1; a > 0; --a) {
                 int b = (int)(splitmix64(&rs) % (uint64_t)(a + 1));
                 int32_t t = c->nbuf[a];
@@ -403,23 +583,66 @@ static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, con
                 c->nbuf[b] = t;
             }
         }
+        Ent top_before[10], first_before = {INFINITY, -1};
+        int64_t top_n = rsize < t10 ? rsize : t10;
+        float r_before = r;
+        if (feat) {
+            for (int64_t i = 0; i < top_n; ++i) top_before[i] = c->R[i];
+            if (rsize > 0) first_before = c->R[0];
+        }
+        ev = INFINITY;
         for (int j = 0; j < nn; ++j) {
             int32_t nb = c->nbuf[j];
             float dn = or_dist32(V->vec + (int64_t)nb * V->vs, q, V->m, V->metric);
+            c->dbuf[j] = dn;
             s.evals++;
             if (dn <= thr_of(r, onep)) { /* close enough to be analysed later */
-                heap_push(c, (Ent){dn, nb});
+                push_capped(c, (Ent){dn, nb}, L, &ev);
                 if (dn <= r && !is_excluded(nb, ex, nex)) insert_R(c, &rsize, k, (Ent){dn, nb}, &r);
             }
         }
-        if (cap_L > 0 && apply_capacity(c, cap_L, thr_of(r, onep))) s.overflow = 1;
-        if (want_live) {
+        if (isfinite(ev) && ev <= thr_of(r, onep)) s.overflow = 1;
+        if (feat) {
+            /* what the row changed: the front of R, R's first entry, r, acceptances */
+            int64_t tn = rsize < t10 ? rsize : t10;
+            int changed = tn != top_n;
+            for (int64_t i = 0; i < tn && !changed; ++i)
+                changed = c->R[i].id != top_before[i].id || c->R[i].d != top_before[i].d;
+            if (changed) F.last_top = s.hops;
+            if (rsize > 0 && (c->R[0].id != first_before.id || c->R[0].d != first_before.d))
+                F.last_d1 = s.hops;
+            if (r != r_before) F.last_r = s.hops;
+            float te = thr_of(r, onep);
+            F.n_s = 0;
+            F.n_r = 0;
+            for (int j = 0; j < nn; ++j) {
+                if (c->dbuf[j] <= te) F.n_s++;
+                for (int64_t i = 0; i < rsize; ++i)
+                    if (c->R[i].id == c->nbuf[j]) {
+                        F.n_r++;
+                        break;
+                    }
+            }
+        }
+        if (o->want_live) {
             int64_t live = 0;
             float t = thr_of(r, onep);
             for (int64_t i = 0; i < c->hsize; ++i) live += (c->heap[i].d <= t);
             if (live > s.max_live) s.max_live = live;
         }
     }
+    if (o->trace) { /* labels: 1 where the front of R does not change after the row's hop */
+        for (int64_t i = 0; i < o->trace_rows; ++i) {
+            float *row = o->trace + i * OR_TRACE_W;
+            if (i < nrow) {
+                row[16] = ((int64_t)o->trace_interval * (i + 1) > F.last_top) ? 1.0f : 0.0f;
+            } else {
+                for (int j = 0; j < OR_TRACE_W; ++j) row[j] = 0.0f;
+                row[16] = -1.0f;
+            }
+        }
+    }
+    if (s.overflow) s.flags |= OR_FLAG_QUEUE_OVERFLOW;
     if (st) *st = s;
     return rsize;
 }
@@ -427,6 +650,15 @@ static int64_t range_search_core(Ctx *c, const VecView *V, const AdjView *G, con
 /* ------------------------------------------------------------------------ */
 /* batched search with threads (Algorithm 1 per query)                      */
 /* ------------------------------------------------------------------------ */
+
+/* Learned stop: BF16 weights, feature standardisation, thresholds (probabilities). */
+typedef struct {
+    const uint16_t *w;
+    const float *mean, *istd;
+    float tau, tau_long;
+    int32_t interval, long_hops; /* long_hops 0: tau throughout */
+} OrStop;
+
 typedef struct {
     const VecView *V;
     const AdjView *G;
@@ -434,13 +666,20 @@ typedef struct {
     int64_t qstride, nq;
     const int32_t *seeds;
     int32_t ns;
-    const int32_t *exclude;
+    const int64_t *ex_off;
+    const int32_t *ex_ids;
     const int32_t *k_arr;
     const float *eps_arr;
-    int32_t k;
+    const int32_t *kind_arr;
+    int32_t k, k_pool;
     float eps;
     int64_t cap_L;
     int32_t order_mode;
+    const OrStop *stop;
+    float stop_z, stop_z_long;
+    float *trace;
+    int64_t trace_rows;
+    int32_t trace_interval;
     int32_t *out_ids;
     float *out_dists;
     int64_t out_stride;
@@ -448,6 +687,13 @@ typedef struct {
     int64_t next;
     pthread_mutex_t mu;
 } SearchJob;
+
+/* sigmoid(z) >= tau  <=>  z >= log(tau / (1 - tau)) */
+static float tau_logit(float tau) {
+    if (tau <= 0.0f) return -INFINITY;
+    if (tau >= 1.0f) return INFINITY;
+    return logf(tau / (1.0f - tau));
+}
 
 static void *search_worker(void *arg) {
     SearchJob *J = (SearchJob *)arg;
@@ -462,13 +708,38 @@ static void *search_worker(void *arg) {
         int64_t qe = qi + 16 < J->nq ? qi + 16 : J->nq;
         for (; qi < qe; ++qi) {
             int32_t k = J->k_arr ? J->k_arr[qi] : J->k;
+            int32_t kp = J->k_pool > k ? J->k_pool : k;
             float eps = J->eps_arr ? J->eps_arr[qi] : J->eps;
-            int32_t ex = J->exclude ? J->exclude[qi] : -1;
+            const int32_t *ex = J->ex_off ? J->ex_ids + J->ex_off[qi] : NULL;
+            int nex = J->ex_off ? (int)(J->ex_off[qi + 1] - J->ex_off[qi]) : 0;
+            SearchOpts o;
+            memset(&o, 0, sizeof(o));
+            o.cap_L = J->cap_L;
+            o.order_mode = J->order_mode;
+            o.order_seed = 0x1234567ull + (uint64_t)qi;
+            o.want_live = J->out_stats != NULL;
+            o.k_user = k;
+            o.kind = J->kind_arr ? J->kind_arr[qi] : 0;
+            if (J->stop) {
+                o.stop_w = J->stop->w;
+                o.stop_mean = J->stop->mean;
+                o.stop_istd = J->stop->istd;
+                o.stop_z = J->stop_z;
+                o.stop_z_long = J->stop_z_long;
+                o.stop_interval = J->stop->interval;
+                o.stop_long_hops = J->stop->long_hops > 0 ? J->stop->long_hops : 0x7fffffff;
+            }
+            if (J->trace) {
+                o.trace = J->trace + qi * J->trace_rows * OR_TRACE_W;
+                o.trace_rows = J->trace_rows;
+                o.trace_interval = J->trace_interval;
+            }
             SearchStats st;
             int64_t rs = range_search_core(&c, J->V, J->G, J->queries + qi * J->qstride,
-                                           J->seeds + qi * J->ns, J->ns, &ex, ex >= 0 ? 1 : 0, k,
-                                           eps, J->cap_L, J->order_mode, 0x1234567ull + (uint64_t)qi,
-                                           J->out_stats != NULL, &st);
+                                           J->seeds + qi * J->ns, J->ns, ex, nex, kp, eps, &o, &st);
+            if (J->trace)
+                for (int64_t i = 0; i < J->trace_rows; ++i)
+                    o.trace[i * OR_TRACE_W + 17] = (float)qi;
             int32_t *oi = J->out_ids + qi * J->out_stride;
             float *od = J->out_dists + qi * J->out_stride;
             for (int64_t j = 0; j < J->out_stride; ++j) {
@@ -481,11 +752,11 @@ static void *search_worker(void *arg) {
                 }
             }
             if (J->out_stats) {
-                int64_t *o = J->out_stats + qi * 4;
-                o[0] = st.hops;
-                o[1] = st.evals;
-                o[2] = st.max_live;
-                o[3] = st.overflow;
+                int64_t *o4 = J->out_stats + qi * 4;
+                o4[0] = st.hops;
+                o4[1] = st.evals;
+                o4[2] = st.max_live;
+                o4[3] = st.flags;
             }
         }
     }
@@ -499,19 +770,27 @@ static void *search_worker(void *arg) {
  *   adj        n x d int32 neighbour ids (row stride adj_stride)
  *   queries    nq x m FP32 (row stride qstride)
  *   seeds      nq x ns seed ids
- *   exclude    nullable; nq ids never placed in R (-1 = none)
- *   k_arr/eps_arr nullable per-query overrides of k/eps
- *   out_ids/out_dists  nq x out_stride, sorted by (dist,id), padded with (-1, +inf)
- *   out_stats  nullable; nq x {hops, evals, max live |S|, overflow}
+ *   ex_off/ex_ids  nullable; CSR lists (nq + 1 offsets) of ids never placed in R
+ *   k_arr/eps_arr/kind_arr  nullable per-query k, eps and kind (1 = exploratory)
+ *   k_pool     R holds max(k, k_pool) entries (the traversal pool)
+ *   stop       nullable learned stop; trace (nullable) nq x trace_rows rows of 20
+ *              floats: 16 features, label, query index, hop, 0
+ *   out_ids/out_dists  nq x out_stride: the first out_stride entries of R sorted by
+ *              (dist,id), padded with (-1, +inf)
+ *   out_stats  nullable; nq x {hops, evals, max live |S|, flags (1 overflow, 16 learned stop)}
  * Returns 0, or -1 on invalid arguments.
  */
 int or_range_search(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t metric,
                     const int32_t *adj, int32_t d, int64_t adj_stride, const float *queries,
                     int64_t nq, int64_t qstride, const int32_t *seeds, int32_t ns,
-                    const int32_t *exclude, const int32_t *k_arr, const float *eps_arr, int32_t k,
-                    float eps, int64_t cap_L, int32_t order_mode, int32_t *out_ids,
+                    const int64_t *ex_off, const int32_t *ex_ids, const int32_t *k_arr,
+                    const float *eps_arr, const int32_t *kind_arr, int32_t k, int32_t k_pool,
+                    float eps, int64_t cap_L, int32_t order_mode, const OrStop *stop, float *trace,
+                    int64_t trace_rows, int32_t trace_interval, int32_t *out_ids,
                     float *out_dists, int64_t out_stride, int64_t *out_stats, int32_t nthreads) {
     if (n <= 0 || m <= 0 || d <= 0 || nq < 0 || ns <= 0 || k < 1 || out_stride < 1) return -1;
+    if (stop && (!stop->w || !stop->mean || !stop->istd || stop->interval < 1)) return -1;
+    if (trace && (trace_rows < 1 || trace_interval < 1)) return -1;
     VecView V = {vec, n, m, vs, metric};
     AdjView G = {adj, adj_stride, NULL, d};
     SearchJob J;
@@ -523,13 +802,24 @@ int or_range_search(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t 
     J.nq = nq;
     J.seeds = seeds;
     J.ns = ns;
-    J.exclude = exclude;
+    J.ex_off = ex_off;
+    J.ex_ids = ex_ids;
     J.k_arr = k_arr;
     J.eps_arr = eps_arr;
+    J.kind_arr = kind_arr;
     J.k = k;
+    J.k_pool = k_pool;
     J.eps = eps;
     J.cap_L = cap_L;
     J.order_mode = order_mode;
+    J.stop = stop;
+    if (stop) {
+        J.stop_z = tau_logit(stop->tau);
+        J.stop_z_long = stop->long_hops > 0 ? tau_logit(stop->tau_long) : J.stop_z;
+    }
+    J.trace = trace;
+    J.trace_rows = trace_rows;
+    J.trace_interval = trace_interval;
     J.out_ids = out_ids;
     J.out_dists = out_dists;
     J.out_stride = out_stride;
@@ -768,8 +1058,10 @@ static int64_t graph_search(Graph *g, const int32_t *seeds, int ns, int64_t qv, 
                             float eps, Ent *out) {
     AdjView G = {g->nbr, g->d, g->cnt, g->d};
     g->n_searches++;
+    SearchOpts o;
+    memset(&o, 0, sizeof(o)); /* unbounded S, row order, no features */
     int64_t rs = range_search_core(&g->ctx, &g->V, &G, g->V.vec + qv * g->V.vs, seeds, ns, NULL,
-                                   0, k, eps, 0, 0, 0, 0, NULL);
+                                   0, k, eps, &o, NULL);
     memcpy(out, g->ctx.R, sizeof(Ent) * (size_t)rs);
     return rs;
 }

@@ -159,6 +159,93 @@ def test_order_independence(eps):
         assert (st[:, :2] == base[2][:, :2]).all()
 
 
+def test_capacity_hand_trace():
+    # alg1_toy case 1 with L = 1: after hop 1 S keeps only 3 (1); pushing 4 (9)
+    # into the full S evicts it, and 4 is within the end-of-hop range 9 -> overflow.
+    # Hop 2 expands 3 (1 checked, out of range); S is empty: 2 hops, not 3.
+    adj, cases = _toy()
+    c = cases[0]
+    pts = np.array(c["points"], np.float32).reshape(-1, 1)
+    ids, ds, st = oracle.range_search(pts, adj, np.array([[7.0]], np.float32), [0], 2, 0.0, cap_L=1)
+    assert ids[0].tolist() == [3, 4] and ds[0].tolist() == [1.0, 9.0]
+    assert st[0, 0] == 2 and st[0, 1] == 6 and st[0, 3] & 1
+
+
+def greedy_walk(x, adj, q, seed, k, eps):
+    """Algorithm 1 with room for one candidate, stated as a walk: from the current
+    vertex, check its unchecked neighbours, keep the k best vertices seen, and
+    move to the closest new neighbour if it lies within the range r(1+eps)
+    measured after the row; otherwise stop. r is the k-th best distance once
+    more than k vertices were accepted, else infinite."""
+    d = lambda i: np.float32(oracle.dist32(x[i], q))
+    onep = np.float32(1.0) + np.float32(eps)
+    R, full = [(d(seed), seed)], False
+
+    def thr():
+        return np.float32(R[k - 1][0]) * onep if full else np.float32(np.inf)
+
+    checked = {seed}
+    cur, hops = R[0], 0
+    while True:
+        hops += 1
+        new = [n for n in adj[cur[1]].tolist() if n not in checked]
+        checked.update(new)
+        cand = [(d(n), n) for n in new]
+        for e in cand:
+            if not full or e[0] <= R[k - 1][0]:
+                R = sorted(R + [e])
+                if len(R) > k:
+                    R, full = R[:k], True
+        live = [e for e in cand if e[0] <= thr()]
+        if not live:
+            break
+        cur = min(live)
+    return [i for _, i in R], hops
+
+
+def test_capacity_one_is_a_greedy_walk():
+    x, adj, _ = built(2000, 24, 30)
+    q = synth.small_int(91, 60, 24, hi=64)
+    for k, eps in ((1, 0.0), (5, 0.1), (10, 0.3)):
+        ids, ds, st = oracle.range_search(x, adj, q, [0], k, eps, cap_L=1)
+        for i in range(q.shape[0]):
+            gi, gh = greedy_walk(x, adj, q[i], 0, k, eps)
+            assert ids[i].tolist() == gi + [-1] * (k - len(gi)), (k, eps, i)
+            assert st[i, 0] == gh, (k, eps, i)
+
+
+@pytest.mark.parametrize("L", [2, 8, 24])
+def test_binding_capacity_is_order_independent(L):
+    # per-push eviction of the largest keeps the L smallest of each row's
+    # survivors whatever the order of the row: ids, counters and flags agree
+    x, adj, _ = built(2000, 24, 30)
+    q = synth.small_int(92, 100, 24, hi=64)
+    base = oracle.range_search(x, adj, q, [0], 10, 0.2, cap_L=L)
+    assert (base[2][:, 3] & 1).any()
+    for mode in (1, 2):
+        ids, ds, st = oracle.range_search(x, adj, q, [0], 10, 0.2, cap_L=L, order_mode=mode)
+        assert (ids == base[0]).all() and (ds == base[1]).all()
+        assert (st[:, :2] == base[2][:, :2]).all() and (st[:, 3] == base[2][:, 3]).all()
+
+
+def test_unflagged_queries_equal_the_unbounded_search():
+    # no live candidate lost <=> the bounded search is Algorithm 1 exactly
+    x, adj, _ = built(2000, 24, 30)
+    q = synth.small_int(93, 200, 24, hi=64)
+    ref = oracle.range_search(x, adj, q, [0], 20, 0.2)
+    mixed = 0
+    for L in (40, 56, 64, 72, 128):
+        ids, ds, st = oracle.range_search(x, adj, q, [0], 20, 0.2, cap_L=L)
+        ok = (st[:, 3] & 1) == 0
+        mixed += ok.any() and (~ok).any()
+        assert (ids[ok] == ref[0][ok]).all() and (st[ok, :2] == ref[2][ok, :2]).all()
+        # at a tight capacity the lost live entries change the work of most queries
+        if L == 40:
+            diff = (ids[~ok] != ref[0][~ok]).any(1) | (st[~ok, :2] != ref[2][~ok, :2]).any(1)
+            assert diff.mean() > 0.5
+    assert mixed >= 2
+
+
 def test_capacity_bound_equals_unbounded():
     x, adj, _ = built(2000, 24, 30)
     q = synth.small_int(98, 100, 24, hi=64)
@@ -168,7 +255,52 @@ def test_capacity_bound_equals_unbounded():
     assert (ids0 == ids1).all() and (st0[:, :2] == st1[:, :2]).all() and (st1[:, 3] == 0).all()
     # a too-small capacity drops live candidates and is reported
     _, _, st2 = oracle.range_search(x, adj, q, [0], 20, 0.2, cap_L=8)
-    assert st2[:, 3].any()
+    assert (st2[:, 3] & 1).any()
+
+
+# ---------------------------------------------------------------- FP32 rerank
+def test_rerank_of_every_vertex_is_the_exact_knn():
+    # integer data: FP32 distances are exact integers, so the rerank of a pool
+    # holding all N vertices is the exact (distance, id) top-k
+    x = synth.small_int(40, 700, 32, hi=256)
+    q = synth.small_int(41, 12, 32, hi=256)
+    pool = np.arange(700, dtype=np.int32)
+    for i in range(12):
+        d = ((x.astype(np.int64) - q[i].astype(np.int64)) ** 2).sum(1)
+        order = np.lexsort((np.arange(700), d))[:15]
+        ids, ds = oracle.rerank(x, q[i], pool[::-1].copy(), 15)
+        assert ids.tolist() == order.tolist()
+        assert ds.tolist() == d[order].astype(np.float64).tolist()
+    # fewer candidates than k: padded; negative ids are not candidates
+    ids, ds = oracle.rerank(x, q[0], np.array([5, -1, 3], np.int32), 4)
+    assert ids[2:].tolist() == [-1, -1] and np.isinf(ds[2:]).all()
+    assert sorted(ids[:2].tolist()) == [3, 5]
+
+
+def test_rerank_ip_orders_by_one_minus_dot():
+    u = synth.small_unit(42, 300, 16)
+    q = synth.small_unit(43, 1, 16)[0]
+    ids, ds = oracle.rerank(u, q, np.arange(300, dtype=np.int32), 5, oracle.IP)
+    dots = u.astype(np.float64) @ q.astype(np.float64)
+    assert ids[0] == int(np.argmax(dots))
+    assert np.allclose(ds, 1.0 - dots[ids], atol=1e-6)
+
+
+# ---------------------------------------------------------------- exclusion lists
+def test_exclusion_lists_exhaustive_equal_brute_force_over_the_rest():
+    # excluded ids enter S and C but never R: with eps = inf every vertex is
+    # checked, so R is the exact top-k of the vertices not excluded
+    x, adj, _ = built(300, 16, 6)
+    q = synth.small_int(44, 10, 16, hi=64)
+    r = synth.rng(45)
+    ex = [r.choice(300, size=r.integers(0, 40), replace=False).tolist() for _ in range(10)]
+    ids, ds, st = oracle.range_search(x, adj, q, [0], 12, float("inf"), exclude=ex)
+    for i in range(10):
+        keep = [j for j in range(300) if j not in set(ex[i])]
+        d = [(oracle.dist32(x[j], q[i]), j) for j in keep]
+        d.sort()
+        assert ids[i].tolist() == [j for _, j in d[:12]]
+        assert st[i, 1] == 300
 
 
 def test_multi_seed_and_dedup():
