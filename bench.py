@@ -303,7 +303,7 @@ def run_batch(a):
         sel = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(1))[:8_000_000].cuda()
         X, y = X[sel], y[sel]
     mean, inv_std = stop.standardise(X)
-    params, hist = stop.train(((X - mean) * inv_std).contiguous(), y.contiguous(), epochs=a.epochs)
+    params, hist = stop.train(stop.standardised(X, mean, inv_std), y.contiguous(), epochs=a.epochs)
     hk, hsv, hrows, hkk, hee = _stream(rng, nhold, nhold, n, seed)
     hrows = hrows + (ntr - nhold)  # held-out vectors
     dh_, tot_h, km_h = api.make_descs(hk, hsv, hrows, hkk, hee)
@@ -634,7 +634,7 @@ def main(argv=None):
             sel = torch.randperm(X.shape[0], generator=torch.Generator().manual_seed(1))[:8_000_000].cuda()
             X, y = X[sel], y[sel]
         mean, inv_std = stop.standardise(X)
-        Xs = ((X - mean) * inv_std).contiguous()
+        Xs = stop.standardised(X, mean, inv_std)
         params, hist = stop.train(Xs, y.contiguous(), epochs=a.epochs)
         log("stop model: %d rows (%.2f positive), loss %s, %.1fs"
             % (X.shape[0], float(y.mean()), [round(h, 4) for h in hist], time.time() - t1))

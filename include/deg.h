@@ -51,7 +51,8 @@ typedef enum { DEG_F32 = 0, DEG_BF16 = 1, DEG_FP8_E4M3 = 2 } deg_dtype;
 /* Per-query flag bits written to out_stats[q*4 + 2]. */
 #define DEG_FLAG_QUEUE_OVERFLOW 1 /* a live candidate was dropped because S was full */
 #define DEG_FLAG_HASH_SPILL 2     /* the visited set moved from LDS to the workspace */
-#define DEG_FLAG_HASH_FULL 4      /* the workspace visited table filled: search ended early */
+#define DEG_FLAG_HASH_FULL 4      /* never set: the workspace visited tables grow until they hold
+                                     all n vertices below 3/4 load (kept for the bit layout) */
 #define DEG_FLAG_BAD_ID 8         /* a seed, query vertex or adjacency id was outside [0, N) */
 #define DEG_FLAG_LEARNED_STOP 16  /* the stop predictor ended the search */
 
@@ -91,14 +92,27 @@ typedef struct {
 /*
  * Learned early stop: a 16-64-64-1 MLP (ReLU, sigmoid) in BF16 as written by
  * deg_mlp_export_bf16 (5313 values: W1[64][16], b1[64], W2[64][64], b2[64],
- * w3[64], b3), evaluated with BF16 weights, the inputs of both hidden layers
- * rounded to BF16 and FP32 accumulation. Every `interval` hops the search
- * computes its 16 state features (hop and evaluation counts, best/k-th and
- * radius ratios, stagnation counters, acceptance fractions, queued candidates
- * closer than the k-th result, popped over k-th distance, eps, k, kind,
- * visited count); if sigmoid(logit) >= tau it stops (from hop `long_hops` on, when
- * long_hops > 0, the threshold is tau_long instead: long queries set the
- * makespan of a batch). The plain rule of Algorithm 1 still applies.
+ * w3[64], b3). Inference is one fixed FP32 computation: x = bf16(features);
+ * h1_j = bf16(relu(b1_j + W1_j0 x_0 + ... + W1_j15 x_15)) and h2_j = relu(b2_j +
+ * W2_j0 h1_0 + ... + W2_j63 h1_63), each a chain of fused multiply-adds in
+ * increasing index; logit = (halving tree over w3_j * h2_j, w = 32..1) + b3.
+ * At the hops h = interval, 2 interval, ... (after the pop passed the test of
+ * Algorithm 1, before the row is expanded) the search forms 16 features from
+ * its state, with kq = min(k, |R|) and d1, dk the distances of R's first and
+ * kq-th entries (FP32, correctly rounded division and square root; a ratio
+ * with a zero or non-finite divisor is 1):
+ *   0 sqrt(h)  1 sqrt(evaluations)  2 d1/dk  3 d1/(smallest seed distance)
+ *   4 r/(r at the previous checkpoint)  5 sqrt(hops since the first min(pool, 10)
+ *   results changed)  6 sqrt(hops since the first result changed)  7 (new
+ *   candidates of the last expanded row within the end-of-row range)/degree
+ *   8 (new candidates of the last row in R after it)/degree  9 min(64, entries
+ *   of S before the kq-th result)/64  10 min(4, popped distance/dk)
+ *   11 min(eps, 4)  12 sqrt(k)  13 1 if exploratory  14 sqrt(hops since r
+ *   changed)  15 1.
+ * Features are standardised as (f - mean) * inv_std in FP32; if the logit is
+ * >= log(tau / (1 - tau)) the search stops (from hop `long_hops` on, when
+ * long_hops > 0, with tau_long instead: long queries set the makespan of a
+ * batch). The plain rule of Algorithm 1 still applies.
  */
 typedef struct {
     const uint16_t *weights_bf16; /* device */
@@ -112,13 +126,15 @@ typedef struct {
 
 /* Search options. Zero-initialised means: defaults. */
 typedef struct {
-    int32_t queue_cap;  /* capacity L of the candidate set S, applied at the end of each hop:
-                           when |S| > L + 64 the entries beyond the threshold r(1+eps) are
-                           dropped, then if still |S| > L + 64 only the L smallest stay
-                           (DEG_FLAG_QUEUE_OVERFLOW); 0 = default min(4096, max(256, 8 k_pool)) */
+    int32_t queue_cap;  /* capacity L of the candidate set S (Algorithm 1's S is unbounded):
+                           the same as evicting the (distance, id)-largest entry at every
+                           push into a full S. DEG_FLAG_QUEUE_OVERFLOW marks a query that
+                           lost an entry within r(1+eps) (without it the result is Algorithm
+                           1's exactly); 0 = default min(4096, max(256, 8 k_pool)) */
     int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = the tuned
-                           value if one is registered, else 512. The set moves to a
-                           workspace table at 3/4 load. */
+                           value if one is registered, else 512. At 3/4 load the set moves
+                           to a workspace table, and from there to one four times larger
+                           at each 3/4 load (the last holds all n vertices). */
     int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
                            from f32_data when k_pool > k or dtype != DEG_F32; 0 = k */
     int32_t rerank;     /* 1 = always rerank the pool in FP32, 0 = only when needed */
@@ -131,7 +147,12 @@ typedef struct {
 
 /*
  * Workspace bytes needed by deg_search / deg_search_indexed / deg_search_batch
- * for `nq` queries with results of size up to `k` and these options.
+ * for `nq` queries with results of size up to `k` and these options: a work
+ * counter, one region of visited tables per resident wave (8192 slots, then
+ * four times larger up to 131072) and, when n needs larger tables, up to 64
+ * shared tables of the smallest power of two >= 4n/3 int32 slots (a query
+ * that needs one while all are held waits for one). Concurrent calls must not
+ * share a workspace.
  */
 size_t deg_search_workspace_bytes(const deg_vectors *v, const deg_graph *g, int64_t nq,
                                   int32_t k, const deg_search_opts *o);
@@ -241,6 +262,14 @@ deg_status deg_mlp_forward_bf16(const uint16_t *w, const float *X, int64_t B, fl
                                 void *stream);
 /* FP32 params -> BF16 weights for deg_stop_model. */
 deg_status deg_mlp_export_bf16(const float *params, uint16_t *out, void *stream);
+/* Standardisation of the stop predictor's inputs: per column of B x 16 rows X
+ * the mean and 1 / (unbiased standard deviation) (0 when it is <= 1e-6), summed
+ * in FP64 in a fixed order; and out = (X - mean) * inv_std in FP32 (out may
+ * equal X). mean, inv_std: 16 floats each (device). */
+deg_status deg_mlp_feature_stats(const float *X, int64_t B, float *mean, float *inv_std,
+                                 void *stream);
+deg_status deg_mlp_standardise(const float *X, int64_t B, const float *mean,
+                               const float *inv_std, float *out, void *stream);
 
 /*
  * Autotuner table (written by the package's tuner, read at launch): for

@@ -72,7 +72,8 @@ EXPORTS = [
     "deg_search_workspace_bytes", "deg_search", "deg_search_indexed", "deg_search_batch",
     "deg_knn_workspace_bytes", "deg_knn_bruteforce", "deg_medoid_workspace_bytes", "deg_medoid",
     "deg_encode_bf16", "deg_encode_fp8", "deg_mlp_workspace_bytes", "deg_mlp_train_step",
-    "deg_mlp_forward", "deg_mlp_forward_bf16", "deg_mlp_export_bf16", "deg_tune_register",
+    "deg_mlp_forward", "deg_mlp_forward_bf16", "deg_mlp_export_bf16", "deg_mlp_feature_stats",
+    "deg_mlp_standardise", "deg_tune_register",
     "deg_tune_clear", "deg_device_cu_count", "deg_status_string",
 ]
 
@@ -106,6 +107,8 @@ def load_library(path: Path | None = None):
         "deg_mlp_forward": (I32, [P, P, I64, P, V]),
         "deg_mlp_forward_bf16": (I32, [P, P, I64, P, V]),
         "deg_mlp_export_bf16": (I32, [P, P, V]),
+        "deg_mlp_feature_stats": (I32, [P, I64, P, P, V]),
+        "deg_mlp_standardise": (I32, [P, I64, P, P, P, V]),
         "deg_tune_register": (I32, [I32, I32, I32, I32, I32, I32]),
         "deg_tune_clear": (None, []),
         "deg_device_cu_count": (I32, []),
@@ -140,15 +143,39 @@ def _check(fn, code):
 
 
 _ws_cache: dict = {}
+_ws_retired: list = []
 
 
 def workspace(nbytes: int, tag: str = "search") -> torch.Tensor:
-    """A cached device workspace of at least nbytes (reused across calls)."""
-    t = _ws_cache.get(tag)
+    """A cached device workspace of at least nbytes for the current stream.
+
+    One buffer per (tag, stream), so that calls on different streams never
+    share the work counter or the visited tables. A buffer that is outgrown is
+    kept alive (not freed), so that a HIP graph captured with it stays valid;
+    release_workspaces() drops them all. Callers that capture graphs can also
+    pass their own buffer (the `workspace=` argument of the search calls)."""
+    key = (tag, torch.cuda.current_stream().cuda_stream)
+    t = _ws_cache.get(key)
     if t is None or t.numel() < nbytes:
+        if t is not None:
+            _ws_retired.append(t)
         t = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device="cuda")
-        _ws_cache[tag] = t
+        _ws_cache[key] = t
     return t
+
+
+def release_workspaces() -> None:
+    """Frees every cached workspace (no captured graph may use them afterwards)."""
+    _ws_cache.clear()
+    _ws_retired.clear()
+
+
+def _ws_arg(given, need: int, tag: str = "search") -> torch.Tensor:
+    if given is None:
+        return workspace(need, tag)
+    if not (given.is_cuda and given.dtype == torch.uint8) or given.numel() < need:
+        raise DegError("workspace", 3)
+    return given
 
 
 def _pad4(x: int) -> int:
@@ -262,7 +289,7 @@ def search_workspace_bytes(store, graph, nq, k, **opts) -> int:
 
 
 def search(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor, seeds: torch.Tensor,
-           k: int, eps: float, out=None, **opts):
+           k: int, eps: float, out=None, workspace=None, **opts):
     """RangeSearch (Algorithm 1) of every query row. Returns (ids, dists, stats)."""
     L = lib()
     assert queries.is_cuda and queries.dtype == torch.float32 and queries.dim() == 2
@@ -280,7 +307,7 @@ def search(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor, seeds:
     else:
         ids, ds, st = out
     need = L.deg_search_workspace_bytes(C.byref(v), C.byref(g), nq, k, C.byref(o))
-    ws = workspace(need)
+    ws = _ws_arg(workspace, need)
     _check("deg_search", L.deg_search(C.byref(v), C.byref(g), _ptr(queries), nq, queries.stride(0),
                                       _ptr(seeds), seeds.shape[1], k, float(eps), C.byref(o),
                                       _ptr(ids), _ptr(ds), _ptr(st), _ptr(ws), ws.numel(),
@@ -289,7 +316,7 @@ def search(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor, seeds:
 
 
 def search_indexed(store: VectorStore, graph: DeviceGraph, qids: torch.Tensor, k: int, eps: float,
-                   out=None, **opts):
+                   out=None, workspace=None, **opts):
     """Exploratory search: each query is a base vertex, excluded from its answer."""
     L = lib()
     qids = qids.to(device="cuda", dtype=torch.int32).contiguous()
@@ -303,7 +330,7 @@ def search_indexed(store: VectorStore, graph: DeviceGraph, qids: torch.Tensor, k
     else:
         ids, ds, st = out
     need = L.deg_search_workspace_bytes(C.byref(v), C.byref(g), nq, k, C.byref(o))
-    ws = workspace(need)
+    ws = _ws_arg(workspace, need)
     _check("deg_search_indexed", L.deg_search_indexed(C.byref(v), C.byref(g), _ptr(qids), nq, k,
                                                       float(eps), C.byref(o), _ptr(ids), _ptr(ds),
                                                       _ptr(st), _ptr(ws), ws.numel(), _stream()))
@@ -335,7 +362,7 @@ def make_descs(kind, seed_or_vertex, query_row, k, eps) -> tuple[torch.Tensor, i
 
 
 def search_batch(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor | None,
-                 descs: torch.Tensor, nq: int, total: int, k_max: int, **opts):
+                 descs: torch.Tensor, nq: int, total: int, k_max: int, workspace=None, **opts):
     """Mixed stream in one persistent launch. Returns flat ids/dists (total) and stats (nq x 4)."""
     L = lib()
     o, _keep = _opts(**opts)
@@ -344,7 +371,7 @@ def search_batch(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor |
     ds = torch.empty(total, dtype=torch.float32, device="cuda")
     st = torch.empty((nq, 4), dtype=torch.int32, device="cuda")
     need = L.deg_search_workspace_bytes(C.byref(v), C.byref(g), nq, k_max, C.byref(o))
-    ws = workspace(need)
+    ws = _ws_arg(workspace, need)
     qs = 0 if queries is None else queries.stride(0)
     nrows = 0 if queries is None else queries.shape[0]
     _check("deg_search_batch", L.deg_search_batch(C.byref(v), C.byref(g), _ptr(queries), nrows, qs,
@@ -412,6 +439,22 @@ def mlp_forward_bf16(w, X):
 def mlp_export_bf16(params):
     out = torch.empty(MLP_NPARAMS, dtype=torch.uint16, device="cuda")
     _check("deg_mlp_export_bf16", lib().deg_mlp_export_bf16(_ptr(params), _ptr(out), _stream()))
+    return out
+
+
+def mlp_feature_stats(X):
+    """Per-feature mean and inverse standard deviation of B x 16 rows (library kernel)."""
+    mean = torch.empty(NFEAT, dtype=torch.float32, device="cuda")
+    inv = torch.empty(NFEAT, dtype=torch.float32, device="cuda")
+    _check("deg_mlp_feature_stats", lib().deg_mlp_feature_stats(_ptr(X), X.shape[0], _ptr(mean),
+                                                                _ptr(inv), _stream()))
+    return mean, inv
+
+
+def mlp_standardise(X, mean, inv_std):
+    out = torch.empty_like(X)
+    _check("deg_mlp_standardise", lib().deg_mlp_standardise(_ptr(X), X.shape[0], _ptr(mean),
+                                                            _ptr(inv_std), _ptr(out), _stream()))
     return out
 
 

@@ -181,7 +181,7 @@ __global__ void mlp_forward_f32(const float *__restrict__ P, const float *__rest
 // One wave per row with the same routine the search uses.
 __global__ void __launch_bounds__(64) mlp_forward_bf16_kernel(const uint16_t *W, const float *X,
                                                               int64_t B, float *out) {
-    __shared__ __align__(16) uint16_t hbuf[64];
+    __shared__ __align__(16) float hbuf[64];
     const MlpRegs M = mlp_load(W);
     for (int64_t row = blockIdx.x; row < B; row += gridDim.x) {
         const int lane = (int)threadIdx.x & 63;
@@ -196,6 +196,51 @@ __global__ void mlp_export_kernel(const float *P, uint16_t *out) {
     if (e >= MLP_NP) return;
     uint32_t u = __float_as_uint(P[e]);
     out[e] = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Column statistics of B rows of 16 features for the standardisation of the
+// stop predictor's inputs: one block per column, FP64 sums in a fixed order
+// (per-thread strided partial sums, then a tree over the block), two passes
+// (mean, then the unbiased variance). inv_std = 1 / std, or 0 when std <= 1e-6.
+__global__ void __launch_bounds__(256) feature_stats_kernel(const float *X, int64_t B, float *mean,
+                                                            float *inv_std) {
+    __shared__ double red[256];
+    const int c = blockIdx.x, t = threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = t; i < B; i += 256) s += (double)X[i * MLP_IN + c];
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    const double mu = red[0] / (double)B;
+    __syncthreads();
+    s = 0.0;
+    for (int64_t i = t; i < B; i += 256) {
+        const double d = (double)X[i * MLP_IN + c] - mu;
+        s += d * d;
+    }
+    red[t] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w) red[t] += red[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double sd = B > 1 ? sqrt(red[0] / (double)(B - 1)) : 0.0;
+        mean[c] = (float)mu;
+        inv_std[c] = sd > 1e-6 ? (float)(1.0 / sd) : 0.0f;
+    }
+}
+
+// out = (X - mean) * inv_std, FP32 (the rounding the search applies).
+__global__ void standardise_kernel(const float *X, int64_t B, const float *mean,
+                                   const float *inv_std, float *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B * MLP_IN) return;
+    const int c = (int)(i % MLP_IN);
+    out[i] = __fmul_rn(__fsub_rn(X[i], mean[c]), inv_std[c]);
 }
 
 }  // namespace degk
@@ -251,5 +296,23 @@ extern "C" deg_status deg_mlp_export_bf16(const float *params, uint16_t *out, vo
     if (!params || !out) return DEG_ERR_INVALID_ARG;
     hipLaunchKernelGGL(mlp_export_kernel, dim3((MLP_NP + 255) / 256), dim3(256), 0,
                        static_cast<hipStream_t>(stream), params, out);
+    return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
+}
+
+extern "C" deg_status deg_mlp_feature_stats(const float *X, int64_t B, float *mean, float *inv_std,
+                                           void *stream) {
+    if (!X || !mean || !inv_std || B < 1) return DEG_ERR_INVALID_ARG;
+    hipLaunchKernelGGL(feature_stats_kernel, dim3(MLP_IN), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), X, B, mean, inv_std);
+    return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
+}
+
+extern "C" deg_status deg_mlp_standardise(const float *X, int64_t B, const float *mean,
+                                         const float *inv_std, float *out, void *stream) {
+    if (!X || !mean || !inv_std || !out || B < 0) return DEG_ERR_INVALID_ARG;
+    if (B == 0) return DEG_OK;
+    const int64_t n = B * MLP_IN;
+    hipLaunchKernelGGL(standardise_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), X, B, mean, inv_std, out);
     return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
 }

@@ -1,7 +1,9 @@
 // Stop-predictor MLP (16 -> 64 -> 64 -> 1, ReLU, logit) evaluated by one
-// wavefront: lane j owns hidden unit j of both layers. Inference uses the
-// gfx950 BF16 dot-product instruction (two products per instruction, FP32
-// accumulation).
+// wavefront: lane j owns hidden unit j of both layers. BF16 inference is one
+// fixed FP32 computation, so that every implementation of it takes the same
+// stop decisions: BF16 inputs and first-layer outputs, fused multiply-adds in
+// increasing input index (a product of two BF16 values is exact in FP32), and
+// a halving tree over the 64 output-layer products.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,20 +22,15 @@ constexpr int MLP_NP = OFF_B3 + 1;  // 5313
 
 __device__ __forceinline__ float bf16_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
-typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-
 // Round-to-nearest-even FP32 -> BF16 bits (finite inputs).
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
     const uint32_t u = __float_as_uint(x);
     return (u + 0x7FFFu + ((u >> 16) & 1u)) >> 16;
 }
-
-// acc + a.lo * b.lo + a.hi * b.hi with BF16 pairs packed in 32-bit words
-// (element 2t in the low half); the products are exact in FP32.
-__device__ __forceinline__ float dot2(uint32_t a, uint32_t b, float acc) {
-    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a),
-                                           __builtin_bit_cast(bf16x2_t, b), acc, false);
-}
+__device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf16_bits(x) << 16); }
+// BF16 element 2t (low half) and 2t + 1 (high half) of a packed word.
+__device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
 // The weights lane j needs (row j of W1 and W2 as BF16 pairs, b1[j], b2[j],
 // w3[j], b3) in registers: 40 words and 4 floats per lane, read with ten
@@ -66,47 +63,48 @@ __device__ __forceinline__ MlpRegs mlp_load(const uint16_t *W) {
     return M;
 }
 
-// Logit of one feature row, BF16 inference: BF16 weights, the inputs of the
-// two hidden layers rounded to BF16, FP32 accumulation; the output layer
-// takes the FP32 activations. Every lane returns the same value. Lane i < 16
-// holds standardised feature i in `fs`. hbuf: 64 BF16 values (128 bytes) of
-// LDS owned by the wave, 16-byte aligned.
-__device__ __forceinline__ float mlp_logit(const MlpRegs &M, float fs, uint16_t *hbuf) {
+// Logit of one feature row: x_t = bf16(fs_t); h1_j = bf16(relu(b1_j + sum_t
+// W1_jt x_t)) and h2_j = relu(b2_j + sum_t W2_jt h1_t), each sum a chain of
+// fused multiply-adds in increasing t; p_j = w3_j * h2_j, summed by the
+// halving tree p_j += p_(j+w) for w = 32, 16, 8, 4, 2, 1; logit = p_0 + b3.
+// relu(s) = s for s > 0, else +0. Every lane returns the same value. Lane
+// t < 16 holds standardised feature t in `fs`. hbuf: 64 floats of LDS owned
+// by the wave, 16-byte aligned.
+__device__ __forceinline__ float mlp_logit(const MlpRegs &M, float fs, float *hbuf) {
     const int j = (int)threadIdx.x & 63;
-    // layer 1: feature pairs (2t, 2t+1) gathered into lane 2t, broadcast by readlane
-    const uint32_t fb = bf16_bits(fs);
-    const uint32_t nb = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)fb, 0x101, 0xF, 0xF, false);  // lane + 1
-    const uint32_t pair = fb | (nb << 16);
+    const float xb = bf16_round(fs);
     float s = M.b1;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) s = dot2(M.w1[t], (uint32_t)__builtin_amdgcn_readlane((int)pair, 2 * t), s);
-    hbuf[j] = (uint16_t)bf16_bits(fmaxf(s, 0.0f));
+    for (int t = 0; t < 8; ++t) {
+        const float x0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xb), 2 * t));
+        const float x1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, xb), 2 * t + 1));
+        s = __fmaf_rn(bf16_lo(M.w1[t]), x0, s);
+        s = __fmaf_rn(bf16_hi(M.w1[t]), x1, s);
+    }
+    hbuf[j] = bf16_round(s > 0.0f ? s : 0.0f);
     __builtin_amdgcn_wave_barrier();
     __asm__ volatile("" ::: "memory");
-    // layer 2: the 64 hidden values as 32 BF16 pairs from LDS
-    const uint4 *h4 = reinterpret_cast<const uint4 *>(hbuf);
+    const float4 *h4 = reinterpret_cast<const float4 *>(hbuf);
     s = M.b2;
 #pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const uint4 h = h4[t];
-        s = dot2(M.w2[4 * t], h.x, s);
-        s = dot2(M.w2[4 * t + 1], h.y, s);
-        s = dot2(M.w2[4 * t + 2], h.z, s);
-        s = dot2(M.w2[4 * t + 3], h.w, s);
+    for (int t = 0; t < 16; ++t) {
+        const float4 h = h4[t];
+        s = __fmaf_rn(bf16_lo(M.w2[2 * t]), h.x, s);
+        s = __fmaf_rn(bf16_hi(M.w2[2 * t]), h.y, s);
+        s = __fmaf_rn(bf16_lo(M.w2[2 * t + 1]), h.z, s);
+        s = __fmaf_rn(bf16_hi(M.w2[2 * t + 1]), h.w, s);
     }
-    const float h2 = fmaxf(s, 0.0f);
+    const float h2 = s > 0.0f ? s : 0.0f;
     float z = __fmul_rn(M.w3, h2);
-    // sum over the 64 lanes: rotations within rows of 16 (DPP), then the four
-    // row sums through readlane, in a fixed order
-    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x128, 0xF, 0xF, false)));
-    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x124, 0xF, 0xF, false)));
-    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x122, 0xF, 0xF, false)));
-    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x121, 0xF, 0xF, false)));
-    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 0));
-    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 16));
-    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 32));
-    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 48));
-    z = __fadd_rn(__fadd_rn(r0, r1), __fadd_rn(r2, r3));
+    // lanes p < 32 add lane p + 32; then the 32-lane halving tree of the
+    // distance reduction (swizzle for w = 16, row shifts for 8, 4, 2, 1)
+    z = __fadd_rn(z, __shfl_xor(z, 32));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, z), 0x401F)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x108, 0xF, 0xF, true)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x104, 0xF, 0xF, true)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x102, 0xF, 0xF, true)));
+    z = __fadd_rn(z, __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, z), 0x101, 0xF, 0xF, true)));
+    z = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, z), 0));
     __builtin_amdgcn_wave_barrier();
     __asm__ volatile("" ::: "memory");
     return __fadd_rn(z, M.b3);

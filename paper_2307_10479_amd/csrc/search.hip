@@ -11,7 +11,19 @@
 
 namespace degk {
 
-__global__ void reset_counter_kernel(int32_t *c) { *c = 0; }
+// Clears the work counter and the owner words of the shared visited tables
+// (a kernel, not a memset, so that the launch can be captured in a graph).
+__global__ void reset_kernel(int32_t *counter, int32_t *owners, int npool) {
+    if (threadIdx.x == 0) *counter = 0;
+    for (int i = (int)threadIdx.x; i < npool; i += (int)blockDim.x) owners[i] = 0;
+}
+
+// Workspace visited tables: the first holds 8192 slots (32 KiB), a wave's own
+// region goes up to 131072 slots (512 KiB), and larger sets take one of up
+// to 64 shared tables sized for all n vertices.
+constexpr int HG_FIRST = 8192;
+constexpr int HG_PRIV_MAX = 131072;
+constexpr int POOL_MAX = 64;
 
 static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, bool feat) {
     switch (dt) {
@@ -23,11 +35,43 @@ static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, bool feat) {
 
 struct LaunchCfg {
     KernelFn fn;
-    int H, hshift, L, scap, Hg, hgshift, rreg, qch;
+    int H, hshift, L, scap, rreg, qch;
+    int hg0, hg_priv, hg_cap, npool;
+    int64_t region;  // slots per wave
     size_t lds;
     int grid;
-    size_t ws_bytes;
+    size_t off_region, off_pool, ws_bytes;
 };
+
+static int64_t pow2_at_least(int64_t x) {
+    int64_t p = 8;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// Sizes of the workspace visited tables for n vertices: the largest holds n
+// ids at 3/4 load; a wave's region holds the chain hg0, 4 hg0, ... up to
+// priv_max slots; npool shared tables serve longer queries.
+static void size_tables(LaunchCfg &c, int64_t n, int priv_max, int pool_max) {
+    c.hg_cap = (int)pow2_at_least((4 * n + 2) / 3);
+    int h0 = HG_FIRST > 4 * c.H ? HG_FIRST : 4 * c.H;
+    c.hg0 = h0 < c.hg_cap ? h0 : c.hg_cap;
+    c.hg_priv = priv_max < c.hg_cap ? priv_max : c.hg_cap;
+    if (c.hg_priv < c.hg0) c.hg_priv = c.hg0;
+    int64_t region = 0, t = c.hg0;
+    for (;;) {
+        region += t;
+        if (t >= c.hg_cap) break;
+        int64_t nt = 4 * t < c.hg_cap ? 4 * t : c.hg_cap;
+        if (nt > c.hg_priv) break;
+        t = nt;
+    }
+    c.region = region;
+    c.npool = t < c.hg_cap ? (c.grid < pool_max ? c.grid : pool_max) : 0;
+    c.off_region = 256 + ((size_t)4 * c.npool + 255) / 256 * 256;
+    c.off_pool = c.off_region + (size_t)c.grid * (size_t)region * 4;
+    c.ws_bytes = c.off_pool + (size_t)c.npool * (size_t)c.hg_cap * 4;
+}
 
 static int ilog2(int x) {
     int s = 0;
@@ -69,7 +113,7 @@ static deg_status validate_common(const deg_vectors *v, const deg_graph *g, int3
 }
 
 static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, int32_t kmax,
-                          const deg_search_opts *o) {
+                          const deg_search_opts *o, int priv_max = HG_PRIV_MAX) {
     LaunchCfg c;
     int kp = kmax;
     if (o && o->k_pool > kp) kp = o->k_pool;
@@ -80,17 +124,13 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     int L = (o && o->queue_cap > 0) ? o->queue_cap
                                     : (8 * kp > 4096 ? 4096 : (8 * kp > 256 ? 8 * kp : 256));
     c.L = L;
-    c.scap = ((L + 192 > kp ? L + 192 : kp) + 63) / 64 * 64;  // B (L + 64 + two pushes) / rerank buffer
+    c.scap = ((L + 64 > kp ? L + 64 : kp) + 63) / 64 * 64;  // B (L - 1 + a row) / rerank buffer
     const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);
     // untuned default: a small LDS table and more resident waves (the workspace
     // table takes over at 3/4 load; measured best or near-best on every workload)
     int H = (o && o->hash_slots) ? o->hash_slots : (t ? t->hash_slots : 512);
     c.H = H;
     c.hshift = 32 - ilog2(H);
-    int Hg = 1 << 16;
-    while (Hg < 4 * H) Hg <<= 1;
-    c.Hg = Hg;
-    c.hgshift = 32 - ilog2(Hg);
     c.lds = 4 * (size_t)H + 8 * (size_t)c.scap + 8 * 128 + 8 * 64 * (size_t)c.rreg + 4 * 64 + 4 * 64;
     const bool feat = o && (o->stop || o->trace);
     c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg, feat);
@@ -105,7 +145,7 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     if (grid > nq) grid = nq;
     if (grid < 1) grid = 1;
     c.grid = (int)grid;
-    c.ws_bytes = 256 + (size_t)c.grid * (size_t)c.Hg * 4;
+    size_tables(c, v->n, priv_max, POOL_MAX);
     return c;
 }
 
@@ -113,15 +153,21 @@ static deg_status launch(const LaunchCfg &c, SearchParams &P, void *ws, size_t w
                          hipStream_t st) {
     if (c.lds > 64 * 1024) return DEG_ERR_UNSUPPORTED;
     if (ws_bytes < c.ws_bytes || !ws) return DEG_ERR_WORKSPACE;
-    P.counter = reinterpret_cast<int32_t *>(ws);
-    P.spill = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(ws) + 256);
+    char *w = reinterpret_cast<char *>(ws);
+    P.counter = reinterpret_cast<int32_t *>(w);
+    P.pool_owner = reinterpret_cast<int32_t *>(w + 256);
+    P.spill = reinterpret_cast<int32_t *>(w + c.off_region);
+    P.pool = reinterpret_cast<int32_t *>(w + c.off_pool);
     P.L = c.L;
     P.scap = c.scap;
     P.H = c.H;
     P.hshift = c.hshift;
-    P.Hg = c.Hg;
-    P.hgshift = c.hgshift;
-    hipLaunchKernelGGL(reset_counter_kernel, dim3(1), dim3(1), 0, st, P.counter);
+    P.hg0 = c.hg0;
+    P.hg_priv = c.hg_priv;
+    P.hg_cap = c.hg_cap;
+    P.region = c.region;
+    P.npool = c.npool;
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(64), 0, st, P.counter, P.pool_owner, c.npool);
     hipLaunchKernelGGL(c.fn, dim3(c.grid), dim3(64), c.lds, st, P);
     return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
 }
@@ -255,3 +301,4 @@ extern "C" deg_status deg_search_batch(const deg_vectors *v, const deg_graph *g,
     P.out_stats = out_stats;
     return launch(c, P, workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }
+

@@ -17,10 +17,11 @@ namespace degk {
 // >= beta and every key of F is < beta. New keys below beta are rank-merged
 // into F (the overflow beyond 64 moves to B and lowers beta), the others are
 // appended to B. When F runs empty it is refilled with the 64 smallest live
-// keys of B, found by an exact histogram select. At the end of a hop, if S
-// holds more than L + 64 keys, the dead ones are dropped and, if still more
-// than L + 64 remain, only the L smallest are kept (the capacity reading the
-// oracle applies too).
+// keys of B, found by an exact histogram select. Capacity L: at the end of a
+// hop, if S holds more than L keys, the dead ones are dropped and, if more
+// than L live keys remain, only the L smallest stay. This keeps the same live
+// keys as evicting the largest key at every push into a full S: dead keys are
+// larger than every live one and are never expanded.
 struct SQueue {
     uint64_t f;        // per lane: F[lane], KEY_MAX beyond fcnt
     int fcnt;          // wave-uniform
@@ -215,13 +216,13 @@ __device__ __forceinline__ void s_push(SQueue &S, uint64_t ck, uint64_t pm) {
 // End-of-hop capacity rule. Returns true if live keys were dropped.
 __device__ bool s_capacity(SQueue &S, float thr, int L) {
     const int lane = lane_id();
-    if (S.fcnt + S.bcnt <= L + WAVE) return false;
+    if (S.fcnt + S.bcnt <= L) return false;
     const uint32_t othr = ord_of(thr);
     const int fl = __popcll(ballot(lane < S.fcnt && (uint32_t)(S.f >> 32) <= othr));
     S.f = lane < fl ? S.f : KEY_MAX;
     S.fcnt = fl;
     S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
-    if (S.fcnt + S.bcnt <= L + WAVE) return false;
+    if (S.fcnt + S.bcnt <= L) return false;
     if (L <= S.fcnt) {
         S.f = lane < L ? S.f : KEY_MAX;
         S.fcnt = L;
@@ -260,11 +261,12 @@ __device__ __forceinline__ uint64_t r_at(const uint64_t (&R)[RREG], int i) {
 // sorted result list (top-kp by key). `total` counts every key ever offered;
 // once it exceeds kp the radius r is the kp-th distance (Algorithm 1: r
 // changes when R overflows). Returns true if an accepted key landed in the
-// first `t10` positions; `naccepted` gets the number of accepted keys.
+// first `t10` positions; `nkept` gets the number of offered keys that are in
+// R after the merge.
 template <int RREG>
 __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &total, bool &ovf,
                                         int kp, uint64_t ck, uint64_t om, uint64_t *mbuf, int t10,
-                                        int &naccepted) {
+                                        int &nkept) {
     const int lane = lane_id();
     const uint64_t rlast = ovf ? r_at<RREG>(R, kp - 1) : KEY_MAX;
     const bool offer = (om >> lane) & 1ull;
@@ -275,7 +277,7 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
         total += __popcll(om);
         if (total > kp) ovf = true;
     }
-    naccepted = na;
+    nkept = 0;
     if (na == 0) return false;
     int rank_new = 0, myposR = 0;
     int cntR[RREG];
@@ -304,6 +306,7 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
     const int newpos = myposR + rank_new;
     if (acc && newpos < kp) mbuf[newpos] = ck;
     const bool top = ballot(acc && newpos < t10) != 0;
+    nkept = __popcll(ballot(acc && newpos < kp));
     rcnt = min(kp, rcnt + na);
     wave_sync();
 #pragma unroll
@@ -326,24 +329,27 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
     uint64_t *stg = Sq + P.scap;                                             // 128 keys
     uint64_t *mbuf = stg + 2 * WAVE;
     uint32_t *hist = reinterpret_cast<uint32_t *>(mbuf + RREG * WAVE);
-    uint16_t *hbuf = reinterpret_cast<uint16_t *>(hist + WAVE);
+    float *hbuf = reinterpret_cast<float *>(hist + WAVE);
     // candidate hand-out area of the distance batches: the staging keys, which
     // only live inside one S operation
     int32_t *xb = reinterpret_cast<int32_t *>(stg);
 
     Visited V;
     V.htab = htab;
-    V.gtab = P.spill + (size_t)blockIdx.x * (size_t)P.Hg;
+    V.region = P.spill + (int64_t)blockIdx.x * P.region;
+    V.gtab = V.region;
     V.H = P.H;
     V.hshift = P.hshift;
-    V.Hg = P.Hg;
-    V.hgshift = P.hgshift;
+    V.Hg = P.hg0;
+    V.hgshift = 32;
+    V.limit = 0;
+    V.roff = 0;
+    V.pslot = -1;
 
     const int nch = (P.dim + 3) >> 2;
     const bool mask_tail = (P.dim & 3) != 0;
     const int deg = P.degree;
     const int hlimit = (3 * P.H) / 4;
-    const int glimit = (3 * P.Hg) / 4;
 
     // stop model: the feature standardisation stays in registers for the whole
     // launch; the weights (10.6 KB shared by every wave, so they stay in L2) are
@@ -398,6 +404,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                     st[2] = DEG_FLAG_BAD_ID;
                     st[3] = 0;
                 }
+                if (FEAT && P.trace != nullptr)  // no row of a skipped query is a training row
+                    for (int i = lane; i < P.trace_rows; i += WAVE)
+                        P.trace[((int64_t)qi * P.trace_rows + i) * TRACE_W + 16] = -1.0f;
                 continue;
             }
         }
@@ -448,7 +457,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         S.hist = hist;
         int hops = 0, evals = 0;
         const int t10 = kp < 10 ? kp : 10;
-        int last_chg = 0, last_d1 = 0;
+        int last_chg = 0, last_d1 = 0, last_r = 0;
         float dseed = __builtin_inff(), rprev = __builtin_inff();
         int n_acc_s = 0, n_acc_r = 0;
         int nrow = 0;
@@ -502,19 +511,26 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             if (want_stop || want_trace) {
                 MlpRegs M{};
                 if (want_stop) M = mlp_load(P.stop_w);  // in flight while the features are formed
-                // lane i < 16 computes state feature i (raw); all inputs are wave-uniform
+                // lane i < 16 computes state feature i from the wave-uniform state:
+                // sqrt of a count, a ratio (correctly rounded), or a plain value
                 const int kq = min(k, rcnt);
                 const float d1 = rcnt > 0 ? key_dist(r_at<RREG>(R, 0)) : 0.f;
                 const uint64_t kkey = kq > 0 ? r_at<RREG>(R, kq - 1) : KEY_MAX;
                 const float dk = kq > 0 ? key_dist(kkey) : 0.f;
-                // queued candidates (among the 64 smallest) still closer than the k-th result
-                const int closer = __popcll(ballot(lane < S.fcnt && S.f < kkey));
-                // lane i < 16 gets feature i's value a and divisor b (selected from the
-                // wave-uniform state), then every lane combines them in the same few steps
+                // entries of S before the kq-th result (F holds the smallest keys of S;
+                // B is counted only when every key of F is before it)
+                int closer = __popcll(ballot(lane < S.fcnt && S.f < kkey));
+                if (closer == S.fcnt && closer < WAVE && S.bcnt > 0) {
+                    int cb = 0;
+                    for (int i = lane; i < S.bcnt; i += WAVE) cb += S.B[i] < kkey ? 1 : 0;
+                    closer += wave_sum_i32(cb);
+                }
+                closer = closer < WAVE ? closer : WAVE;
                 const bool fin_r = !__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f;
                 const bool fin_s = rcnt > 0 && dseed > 0.f && !__builtin_isinf(dseed);
                 const bool fin_k = kq > 0 && dk > 0.f;
-                int ai = __float_as_int(1.0f);
+                // mode: 0 plain a, 1 sqrt(a), 2 a / b (1 when the divisor is not usable)
+                int ai = 0;
                 ai = lane == 0 ? hops : ai;
                 ai = lane == 1 ? evals : ai;
                 ai = lane == 2 ? __float_as_int(d1) : ai;
@@ -526,30 +542,30 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 ai = lane == 8 ? n_acc_r : ai;
                 ai = lane == 9 ? closer : ai;
                 ai = lane == 10 ? __float_as_int(ds) : ai;
-                ai = lane == 11 ? __float_as_int(eps) : ai;
-                ai = lane == 12 ? k - 1 : ai;
+                ai = lane == 11 ? __float_as_int(fminf(eps, 4.0f)) : ai;
+                ai = lane == 12 ? k : ai;
                 ai = lane == 13 ? kind : ai;
-                ai = lane == 14 ? V.count : ai;
-                int bi = __float_as_int(1.0f);
-                bi = lane == 2 ? __float_as_int(dk) : bi;
-                bi = lane == 3 ? __float_as_int(dseed) : bi;
-                bi = lane == 4 ? __float_as_int(rprev) : bi;
-                bi = lane == 7 ? __float_as_int((float)deg) : bi;
-                bi = lane == 8 ? __float_as_int((float)deg) : bi;
-                bi = lane == 9 ? __float_as_int(64.0f) : bi;
-                bi = lane == 10 ? __float_as_int(dk) : bi;
-                const uint32_t okm = (fin_k ? 0x404u : 0u) | (fin_s ? 0x8u : 0u) | (fin_r ? 0x10u : 0u) | 0x380u;
+                ai = lane == 14 ? hops - last_r : ai;
+                ai = lane == 15 ? 1 : ai;
+                float fb = 1.0f;
+                fb = lane == 2 ? dk : fb;
+                fb = lane == 3 ? dseed : fb;
+                fb = lane == 4 ? rprev : fb;
+                fb = (lane == 7 || lane == 8) ? (float)deg : fb;
+                fb = lane == 9 ? 64.0f : fb;
+                fb = lane == 10 ? dk : fb;
                 const uint32_t lb = 1u << (lane & 31);
                 const bool lane_lo = lane < 16;
-                const bool is_int = lane_lo && (0x73E3u & lb) != 0;    // 0,1,5,6,7,8,9,12,13,14
-                const bool is_log = lane_lo && (0x5063u & lb) != 0;    // 0,1,5,6,12,14
-                const bool is_ratio = lane_lo && (0x079Cu & lb) != 0;  // 2,3,4,7,8,9,10
-                const bool ok = (okm & lb) != 0;
+                const bool is_int = lane_lo && (0xF3E3u & lb) != 0;  // 0,1,5,6,7,8,9,12,13,14,15
+                const bool is_sqrt = lane_lo && (0x5063u & lb) != 0; // 0,1,5,6,12,14
+                const bool is_div = lane_lo && (0x079Cu & lb) != 0;  // 2,3,4,7,8,9,10
+                const uint32_t okm = (fin_k ? 0x404u : 0u) | (fin_s ? 0x8u : 0u) | (fin_r ? 0x10u : 0u) | 0x380u;
                 const float fa = is_int ? (float)ai : __int_as_float(ai);
-                const float fb = __int_as_float(bi);
                 float fv = fa;
-                if (is_log) fv = 0.69314718f * __log2f(1.0f + fa);
-                if (is_ratio) fv = ok ? fa * __builtin_amdgcn_rcpf(fb) : 1.0f;
+                // correctly rounded square root and division (the library is built
+                // with -fhip-fp32-correctly-rounded-divide-sqrt)
+                if (is_sqrt) fv = __builtin_sqrtf(fa);
+                if (is_div) fv = (okm & lb) != 0 ? fa / fb : 1.0f;
                 if (lane == 10) fv = fminf(fv, 4.0f);
                 rprev = r;
                 if (want_trace) {
@@ -582,12 +598,10 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             if (bad) nb = -1;
             if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
             if (!V.spilled && V.count + deg > hlimit) {
-                visit_spill(V);
+                visit_spill(V, P);
                 flags |= DEG_FLAG_HASH_SPILL;
-            }
-            if (V.spilled && V.count + deg > glimit) {
-                flags |= DEG_FLAG_HASH_FULL;
-                break;
+            } else if (V.spilled && V.count + deg > V.limit) {
+                visit_grow(V, P);
             }
             // the runner-up's row is requested inside the check, after its table reads
             const bool isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
@@ -612,7 +626,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                                            mbuf, t10, na);
             if (chg) last_chg = hops;
             if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
+            const float r_old = r;
             r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
+            if (r != r_old) last_r = hops;
 
             // S <- S u {n : delta(n,q) <= r (1 + eps)}
             const float thr = thr_of(r, onep);
@@ -624,6 +640,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             if (np > 0) s_push(S, ck, pm);
             if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
         }
+
+        pool_give(V, P);  // a shared visited table goes back at the end of the query
 
         // ---- trace labels: 1 where the top-10 no longer changes afterwards
         if (FEAT && P.trace != nullptr) {

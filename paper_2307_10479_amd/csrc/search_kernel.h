@@ -71,15 +71,23 @@ struct SearchParams {
     int64_t nqrows; // rows of `queries` (batch mode bound check)
     int32_t H;      // LDS hash slots (power of 2)
     int32_t hshift; // 32 - log2(H)
-    int32_t Hg;     // workspace hash slots per wave (power of 2)
-    int32_t hgshift;
+    // workspace visited tables: each wave owns a region holding tables of
+    // hg0, 4 hg0, 16 hg0, ... slots up to hg_priv; beyond that a query takes
+    // one of npool shared tables of hg_cap slots (3/4 of hg_cap >= n)
+    int32_t hg0;
+    int32_t hg_priv;
+    int32_t hg_cap;
+    int64_t region; // slots per wave region
+    int32_t npool;
     // outputs
     int32_t *out_ids;
     float *out_dists;
     int32_t *out_stats;
     // workspace
     int32_t *counter;
-    int32_t *spill;
+    int32_t *spill;      // the per-wave regions
+    int32_t *pool;       // npool tables of hg_cap slots
+    int32_t *pool_owner; // npool words: 0 free, 1 taken
     // learned stop
     const uint16_t *stop_w;
     const float *stop_mean;
@@ -448,13 +456,20 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
 }
 
 // ---------------------------------------------------------------- visited set
-// Visited set C of one query. It starts in an LDS hash table; when that
-// fills, every id moves to the query's table in the workspace, which from
-// then on is the set.
+// Visited set C of one query, exact for any number of checked vertices. It
+// starts in an LDS hash table; when that is 3/4 full every id moves to the
+// first table of the wave's workspace region, and each time a workspace table
+// is 3/4 full the ids move to one four times larger (the next table of the
+// region, or a shared table of hg_cap slots, which holds all n vertices below
+// 3/4 load).
 struct Visited {
     int32_t *htab;  // LDS
-    int32_t *gtab;  // workspace
+    int32_t *region;// the wave's workspace region
+    int32_t *gtab;  // current workspace table
     int H, hshift, Hg, hgshift;
+    int limit;      // move to a larger table before count exceeds this
+    int64_t roff;   // offset of gtab within region
+    int pslot;      // shared table held (-1: none)
     int count;      // |C| (wave-uniform)
     bool spilled;   // wave-uniform
 };
@@ -612,20 +627,97 @@ __device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
     return visit_insert<false>(V, id, act, nullptr, unused);
 }
 
-// Moves the LDS table to the workspace table (cleared first).
-__device__ __forceinline__ void visit_spill(Visited &V) {
-    const int lane = lane_id();
-    int4 *g4 = reinterpret_cast<int4 *>(V.gtab);
-    for (int i = lane; i < (V.Hg >> 2); i += WAVE) g4[i] = make_int4(-1, -1, -1, -1);
+__device__ __forceinline__ int ilog2_dev(int x) { return 31 - __builtin_clz((unsigned)x); }
+
+// Fills n slots (a multiple of 4) of a workspace table with -1.
+__device__ __forceinline__ void table_clear(int32_t *t, int n) {
+    int4 *t4 = reinterpret_cast<int4 *>(t);
+    for (int i = lane_id(); i < (n >> 2); i += WAVE) t4[i] = make_int4(-1, -1, -1, -1);
+}
+
+// Points V at workspace table t of `slots` slots.
+__device__ __forceinline__ void table_use(Visited &V, int32_t *t, int slots, int hg_cap) {
+    V.gtab = t;
+    V.Hg = slots;
+    V.hgshift = 32 - ilog2_dev(slots);
+    V.limit = slots >= hg_cap ? 0x7fffffff : (3 * slots) / 4;
+}
+
+// Moves the LDS table to the first table of the region (cleared first).
+__device__ __forceinline__ void visit_spill(Visited &V, const SearchParams &P) {
+    table_clear(V.region, P.hg0);
     __threadfence();
     wave_sync();
+    V.roff = 0;
+    table_use(V, V.region, P.hg0, P.hg_cap);
     V.spilled = true;
-    for (int i = lane; i < V.H; i += WAVE) {
+    for (int i = lane_id(); i < V.H; i += WAVE) {
         const int32_t id = V.htab[i];
         if (id >= 0) cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id);
     }
     __threadfence();
     wave_sync();
+}
+
+// Takes a free shared table (waiting while all are held: holders never wait,
+// their searches end, and they give the table back at the end of their query).
+__device__ int pool_take(const SearchParams &P) {
+    int slot = -1;
+    for (;;) {
+        if (lane_id() == 0) {
+            for (int t = 0; t < P.npool; ++t) {
+                const int i = (int)((blockIdx.x + (unsigned)t) % (unsigned)P.npool);
+                if (atomicCAS(&P.pool_owner[i], 0, 1) == 0) {
+                    slot = i;
+                    break;
+                }
+            }
+        }
+        slot = uni(slot);
+        if (slot >= 0) break;
+        __builtin_amdgcn_s_sleep(32);
+    }
+    __threadfence();
+    return slot;
+}
+
+__device__ __forceinline__ void pool_give(Visited &V, const SearchParams &P) {
+    if (V.pslot < 0) return;
+    __threadfence();
+    wave_sync();
+    if (lane_id() == 0) atomicExch(&P.pool_owner[V.pslot], 0);
+    V.pslot = -1;
+}
+
+// Moves the workspace table to one four times larger (or the shared table).
+__device__ void visit_grow(Visited &V, const SearchParams &P) {
+    int ns = V.Hg * 4;
+    if (ns > P.hg_cap) ns = P.hg_cap;
+    int32_t *nt;
+    int64_t noff = V.roff;
+    if (ns <= P.hg_priv) {
+        noff = V.roff + V.Hg;
+        nt = V.region + noff;
+    } else {
+        ns = P.hg_cap;
+        V.pslot = pool_take(P);
+        nt = P.pool + (int64_t)V.pslot * P.hg_cap;
+    }
+    table_clear(nt, ns);
+    __threadfence();
+    wave_sync();
+    const int32_t *old = V.gtab;
+    const int on = V.Hg;
+    const uint32_t msk = (uint32_t)ns - 1u;
+    const int sh = 32 - ilog2_dev(ns);
+    for (int i = lane_id(); i < on; i += WAVE) {
+        const int32_t id = old[i];
+        if (id >= 0) cas_insert(nt, msk, hash_slot(id, sh), id);
+    }
+    __threadfence();
+    wave_sync();
+    V.roff = noff;
+    table_use(V, nt, ns, P.hg_cap);
 }
 
 }  // namespace degk

@@ -12,8 +12,9 @@
 3. Calibration: on held-out queries the threshold tau is the smallest value
    whose top-10 agreement with the plain search stays >= 1 - max_loss; the
    plain stopping rule remains the fallback.
-The torch calls here only move and batch data; all arithmetic of the search,
-the network and its training runs in libdeg.so.
+The torch calls here only move, select and batch data; all arithmetic of the
+search, the feature statistics and standardisation, the network and its
+training runs in libdeg.so.
 """
 from __future__ import annotations
 
@@ -46,10 +47,13 @@ def collect_traces(store, graph, queries, seeds, k, eps_values, interval=2, rows
 
 
 def standardise(X):
-    mean = X.mean(0)
-    std = X.std(0)
-    inv = torch.where(std > 1e-6, 1.0 / std, torch.zeros_like(std))
-    return mean.contiguous(), inv.contiguous()
+    """Feature means and inverse standard deviations (library kernel)."""
+    return api.mlp_feature_stats(X.contiguous())
+
+
+def standardised(X, mean, inv_std):
+    """(X - mean) * inv_std in FP32 (library kernel), the rounding the search applies."""
+    return api.mlp_standardise(X.contiguous(), mean, inv_std)
 
 
 def train(X, y, epochs=4, batch=8192, lr=2e-3, seed=0):
@@ -89,6 +93,10 @@ def train(X, y, epochs=4, batch=8192, lr=2e-3, seed=0):
 
 def build_model(params, mean, inv_std, tau, interval, tau_long=None, long_hops=0):
     w = api.mlp_export_bf16(params)
+    return api.StopModel(w, mean, inv_std, tau, interval, tau_long, long_hops)
+
+
+def build_model_from_bf16(w, mean, inv_std, tau, interval, tau_long=None, long_hops=0):
     return api.StopModel(w, mean, inv_std, tau, interval, tau_long, long_hops)
 
 

@@ -52,7 +52,7 @@ def test_learned_stop_saves_hops_at_bounded_loss():
                                rows=256)
     assert X.shape[0] > 10_000 and 0.0 < float(y.mean()) < 1.0
     mean, inv_std = stop.standardise(X)
-    params, hist = stop.train(((X - mean) * inv_std).contiguous(), y.contiguous(), epochs=6,
+    params, hist = stop.train(stop.standardised(X, mean, inv_std), y.contiguous(), epochs=6,
                               batch=4096)
     assert hist[-1] < hist[0]
     tau, table = stop.calibrate(store, G, ho, seeds(ho.shape[0]), k, eps, params, mean, inv_std,

@@ -232,6 +232,7 @@ def test_mlp_adam_step_vs_oracle(A):
 
 
 def test_mlp_bf16_forward(A):
+    # BF16 inference is one fixed FP32 computation: bit-identical to the oracle's
     P, X, _ = _mlp_data(700, 13)
     Pt = dev(P.astype(np.float32))
     say("mlp bf16")
@@ -240,14 +241,8 @@ def test_mlp_bf16_forward(A):
     torch.cuda.synchronize()
     wb = w.cpu().numpy()
     assert (wb == oracle.bf16_encode(P.astype(np.float32))).all()
-    Pb = oracle.bf16_decode(wb).astype(np.float64)
-    rz = oracle.mlp_logits_bf16(Pb, X)
-    err = np.abs(z.cpu().numpy().astype(np.float64) - rz) / (1.0 + np.abs(rz))
-    # FP32 against FP64 accumulation: ~1e-6. A hidden value within that of a
-    # BF16 rounding midpoint may round the other way on one side (one BF16
-    # step of one unit, a few 1e-3 at most); such rows are rare.
-    assert err.max() <= 1e-2
-    assert (err <= 1e-4).mean() >= 0.98
+    rz = oracle.mlp_logits_bf16(wb, X)
+    assert (z.cpu().numpy() == rz).all()
 
 
 # ---------------------------------------------------------------- batch
@@ -380,10 +375,15 @@ def test_hip_graph_capture_replays(A):
         with torch.cuda.graph(cg, stream=s):
             A.search(store, g, Q, seeds, 10, 0.1, out=out)
     torch.cuda.synchronize()
+    big = dev(synth.small_int(20, 4000, 32, hi=256))
     for rep in range(4):
         for t in out:
             t.fill_(-7)
         A.search(store, g, Q[:5], seeds[:5], 3, 0.0)       # unrelated eager work
+        # eager work that needs a larger workspace than the captured one: the
+        # captured buffer must stay allocated and untouched by it
+        with torch.cuda.stream(s):
+            A.search(store, g, big, dev(np.zeros((4000, 1), np.int32)), 100, 0.2, hash_slots=256)
         torch.cuda.synchronize()
         cg.replay()
         torch.cuda.synchronize()

@@ -313,15 +313,20 @@ def test_parity_cfg2_full_size_sampled(A):
     assert seed == oracle.medoid(base)  # integer data: the GPU medoid equals the oracle's
     seeds = dev(np.full((q.shape[0], 1), seed, np.int32))
     sample = synth.rng(70).choice(q.shape[0], size=300, replace=False)
-    for eps, L in ((0.0, 256), (0.1, 256), (0.15, 1024)):
-        say("cfg2 eps", eps, "L", L)
-        ids, ds, st = A.search(store32, G, dev(q), seeds, 10, eps, queue_cap=L)
-        ids16, ds16, st16 = A.search(store16, G, dev(q), seeds, 10, eps, queue_cap=L)
+    # the last settings are the benchmark's operating points (eps 0.19 with the
+    # capacities it sweeps, 256 LDS visited slots)
+    for eps, L, hs in ((0.0, 256, 0), (0.1, 256, 0), (0.15, 1024, 0), (0.19, 1024, 256),
+                       (0.19, 2048, 256), (0.19, 4096, 256)):
+        say("cfg2 eps", eps, "L", L, "hash slots", hs)
+        ids, ds, st = A.search(store32, G, dev(q), seeds, 10, eps, queue_cap=L, hash_slots=hs)
+        ids16, ds16, st16 = A.search(store16, G, dev(q), seeds, 10, eps, queue_cap=L,
+                                     hash_slots=hs)
         torch.cuda.synchronize()
         ids, ds, st = ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()
         ref = oracle.range_search(base, adj, q[sample], [seed], 10, eps, cap_L=L)
         assert_parity((ids[sample], ds[sample], st[sample]), ref, "cfg2 eps=%g L=%d" % (eps, L))
         ovf = (st[sample, 2] & A.FLAG_QUEUE_OVERFLOW) != 0
-        assert (ovf == (ref[2][:, 3] != 0)).all()
+        assert (ovf == ((ref[2][:, 3] & 1) != 0)).all()
+        assert (st[:, 2] & A.FLAG_HASH_FULL == 0).all()
         # BF16 traversal is lossless on integer data below 256: same result
         assert (ids16.cpu().numpy() == ids).all() and (ds16.cpu().numpy() == ds).all()
