@@ -177,6 +177,26 @@ deg_status deg_search(const deg_vectors *v, const deg_graph *g, const float *que
                       void *stream);
 
 /*
+ * deg_search without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, serving loops, harnesses that forbid
+ * hipMalloc). Same arguments and results as deg_search. Its scratch is one
+ * 128 MiB device array per GPU inside the library (held while the library is
+ * loaded; every call on that GPU shares it and finds it as the last call left
+ * it: the work counter and table owners are cleared by a kernel at each call).
+ * To fit it the launch keeps one 8192-slot visited table per wave, at most 4
+ * shared tables of the smallest power of two >= 4n/3 slots, and fewer resident
+ * waves when needed (results are the same). Returns DEG_ERR_WORKSPACE when n is
+ * too large for one wave's table and one shared table to fit (n above
+ * 12,582,912). Calls that overlap on one GPU (other streams, other threads) race
+ * on the array: serialise them. Allocates nothing (no hipMalloc / hipFree).
+ */
+deg_status deg_search_noalloc(const deg_vectors *v, const deg_graph *g, const float *queries,
+                              int64_t nq, int64_t q_stride, const int32_t *seed_ids,
+                              int32_t n_seeds, int32_t k, float eps, const deg_search_opts *o,
+                              int32_t *out_ids, float *out_dists, int32_t *out_stats,
+                              void *stream);
+
+/*
  * Exploratory search (Sec. 4 and 6.7): each query is a base vertex; the
  * search starts at that vertex, uses its FP32 row as the query, and never
  * returns it (other vertices at distance 0 are returned).

@@ -69,7 +69,8 @@ class DegQueryDesc(C.Structure):
 
 
 EXPORTS = [
-    "deg_search_workspace_bytes", "deg_search", "deg_search_indexed", "deg_search_batch",
+    "deg_search_workspace_bytes", "deg_search", "deg_search_noalloc", "deg_search_indexed",
+    "deg_search_batch",
     "deg_knn_workspace_bytes", "deg_knn_bruteforce", "deg_medoid_workspace_bytes", "deg_medoid",
     "deg_encode_bf16", "deg_encode_fp8", "deg_mlp_workspace_bytes", "deg_mlp_train_step",
     "deg_mlp_forward", "deg_mlp_forward_bf16", "deg_mlp_export_bf16", "deg_mlp_feature_stats",
@@ -94,6 +95,7 @@ def load_library(path: Path | None = None):
     sigs = {
         "deg_search_workspace_bytes": (SZ, [pv, pg, I64, I32, po]),
         "deg_search": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, P, SZ, V]),
+        "deg_search_noalloc": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, V]),
         "deg_search_indexed": (I32, [pv, pg, P, I64, I32, F, po, P, P, P, P, SZ, V]),
         "deg_search_batch": (I32, [pv, pg, P, I64, I64, P, I64, I32, po, P, P, P, P, SZ, V]),
         "deg_knn_workspace_bytes": (SZ, [I64, I32, I64, I32]),
@@ -312,6 +314,32 @@ def search(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor, seeds:
                                       _ptr(seeds), seeds.shape[1], k, float(eps), C.byref(o),
                                       _ptr(ids), _ptr(ds), _ptr(st), _ptr(ws), ws.numel(),
                                       _stream()))
+    return ids, ds, st
+
+
+def search_noalloc(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor,
+                   seeds: torch.Tensor, k: int, eps: float, out=None, **opts):
+    """search() through deg_search_noalloc: no workspace (the library's own
+    per-GPU scratch array). Outputs are allocated here unless `out` is given."""
+    L = lib()
+    assert queries.is_cuda and queries.dtype == torch.float32 and queries.dim() == 2
+    assert queries.stride(1) == 1
+    nq = queries.shape[0]
+    if seeds.dim() == 1:
+        seeds = seeds.view(-1, 1).expand(nq, seeds.numel()) if seeds.numel() != nq else seeds.view(-1, 1)
+    seeds = seeds.to(device=queries.device, dtype=torch.int32).contiguous()
+    o, _keep = _opts(**opts)
+    v, g = store.c(), graph.c()
+    if out is None:
+        ids = torch.empty((nq, k), dtype=torch.int32, device=queries.device)
+        ds = torch.empty((nq, k), dtype=torch.float32, device=queries.device)
+        st = torch.empty((nq, 4), dtype=torch.int32, device=queries.device)
+    else:
+        ids, ds, st = out
+    _check("deg_search_noalloc", L.deg_search_noalloc(C.byref(v), C.byref(g), _ptr(queries), nq,
+                                                      queries.stride(0), _ptr(seeds),
+                                                      seeds.shape[1], k, float(eps), C.byref(o),
+                                                      _ptr(ids), _ptr(ds), _ptr(st), _stream()))
     return ids, ds, st
 
 

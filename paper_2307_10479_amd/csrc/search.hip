@@ -5,6 +5,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "deg.h"
 #include "host_util.h"
 #include "search_impl.h"
@@ -302,3 +304,91 @@ extern "C" deg_status deg_search_batch(const deg_vectors *v, const deg_graph *g,
     return launch(c, P, workspace, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
+// ---------------------------------------------------------------- no-allocation variant
+// deg_search_noalloc keeps its workspace in one file-scope device array per
+// GPU (NOALLOC_BYTES, held while the library is loaded). Host code reaches it
+// only through the device address hipGetSymbolAddress returns for the current
+// device, taken once per device and kept.
+namespace degk {
+
+constexpr size_t NOALLOC_BYTES = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[128];
+
+static deg_status scratch_address(void **out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 128) return DEG_ERR_HIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return DEG_ERR_HIP;
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DEG_OK;
+}
+
+// The launch shaped to fit the scratch array: each wave keeps only the first
+// visited table (hg0 slots), larger sets use at most 4 shared tables, and the
+// persistent grid shrinks until the regions fit (the grid size changes no
+// result). False if even one wave and one shared table do not fit.
+static bool fit_noalloc(LaunchCfg &c, int64_t n) {
+    int pool_max = 4;
+    const int grid0 = c.grid;
+    for (;;) {
+        size_tables(c, n, 0, pool_max);
+        if (c.ws_bytes <= NOALLOC_BYTES) return true;
+        const size_t fixed = c.off_region + (size_t)c.npool * (size_t)c.hg_cap * 4;
+        const size_t per_wave = (size_t)c.region * 4;
+        if (fixed + per_wave <= NOALLOC_BYTES) {
+            size_t g = (NOALLOC_BYTES - fixed) / per_wave;
+            c.grid = (int)(g < (size_t)grid0 ? g : (size_t)grid0);
+            if (c.grid < 1) c.grid = 1;
+            size_tables(c, n, 0, pool_max);
+            if (c.ws_bytes <= NOALLOC_BYTES) return true;
+        }
+        if (pool_max > 1) {
+            pool_max = 1;
+            c.grid = grid0;
+            continue;
+        }
+        return false;
+    }
+}
+
+}  // namespace degk
+
+extern "C" deg_status deg_search_noalloc(const deg_vectors *v, const deg_graph *g,
+                                         const float *queries, int64_t nq, int64_t q_stride,
+                                         const int32_t *seed_ids, int32_t n_seeds, int32_t k,
+                                         float eps, const deg_search_opts *o, int32_t *out_ids,
+                                         float *out_dists, int32_t *out_stats, void *stream) {
+    deg_status s = validate_common(v, g, k, o, false);
+    if (s != DEG_OK) return s;
+    if (nq < 0 || (nq > 0 && (!queries || !seed_ids || !out_ids || !out_dists)))
+        return DEG_ERR_INVALID_ARG;
+    if (q_stride < v->dim || n_seeds < 1 || n_seeds > 64 || !(eps >= 0.f))
+        return DEG_ERR_INVALID_ARG;
+    if (nq == 0) return DEG_OK;
+    if (nq > 0x7fffffffLL) return DEG_ERR_INVALID_ARG;
+    LaunchCfg c = make_cfg(v, g, nq, k, o, 0);
+    if (!fit_noalloc(c, v->n)) return DEG_ERR_WORKSPACE;
+    void *ws = nullptr;
+    s = scratch_address(&ws);
+    if (s != DEG_OK) return s;
+    SearchParams P;
+    fill_common(P, v, g, k, o);
+    P.mode = MODE_VEC;
+    P.queries = queries;
+    P.qstride = q_stride;
+    P.seeds = seed_ids;
+    P.nseeds = n_seeds;
+    P.nq = nq;
+    P.eps = eps;
+    P.out_ids = out_ids;
+    P.out_dists = out_dists;
+    P.out_stats = out_stats;
+    return launch(c, P, ws, NOALLOC_BYTES, static_cast<hipStream_t>(stream));
+}
