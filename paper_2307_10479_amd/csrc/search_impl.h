@@ -466,6 +466,11 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         // S at the previous pop (the next pop in about nine hops of ten) and the
         // closest new candidate of the previous hop
         int32_t run_v = -1, run_nb = -1, spec_v = -1, spec_nb = -1;
+        // workspace-table slots of run_v's neighbours, read during the previous hop
+        // (after its claims) for the probe of the next pop if that is run_v
+        int32_t pv = -1;
+        const int32_t *pv_tab = nullptr;
+        int4 pa = make_int4(-1, -1, -1, -1), pb = pa;
 
         // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
         if (!bad_query) {
@@ -603,16 +608,42 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             } else if (V.spilled && V.count + deg > V.limit) {
                 visit_grow(V, P);
             }
-            // the runner-up's row is requested inside the check, after its table reads
-            const bool isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
+            bool isnew;
+            if (V.spilled && s == pv && V.gtab == pv_tab) {
+                // the first probe round was read ahead: no table round trip here
+                run_nb = *pf;
+                int32_t unused = 0;
+                isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
+                                                   hash_slot(nb, V.hgshift), nb, nb >= 0, nullptr,
+                                                   unused, pa, pb);
+            } else {
+                // the runner-up's row is requested inside the check, after its table reads
+                isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
+            }
+            // read ahead the table slots of run_v's neighbours (run_v is the next pop
+            // in about nine hops of ten): issued after this hop's claims, so nothing
+            // is inserted between these reads and their use
+            auto spec = [&]() {
+                if (V.spilled && run_v >= 0) {
+                    spec_read(V, run_nb, lane < deg && run_nb >= 0 && (int64_t)run_nb < P.n, pa, pb);
+                    pv = run_v;
+                    pv_tab = V.gtab;
+                } else {
+                    pv = -1;
+                }
+            };
             const uint64_t nm = ballot(isnew);
             const int cnt = __popcll(nm);
             V.count += cnt;
             evals += cnt;
             n_acc_s = 0;
             n_acc_r = 0;
-            if (cnt == 0) continue;
-            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb);
+            if (cnt == 0) {
+                spec();
+                continue;
+            }
+            // the table reads go out right after the new rows' loads
+            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb, spec);
             const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
 
             // the closest new candidate is the likely next pop: load its row now

@@ -378,10 +378,16 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
 // group go back through xb[64..128) to the candidates' own lanes. This takes
 // the place of the per-group bit scans and cross-lane reads of batch_dist_g.
 // xb: 128 words of LDS owned by the calling wave.
-template <int DT, int METRIC, int QCH, bool F32ROWS, int G>
+struct NoHook {
+    __device__ __forceinline__ void operator()() const {}
+};
+
+// `hook` runs once, after the row loads of the first round are issued and
+// before any of them is used (work that should overlap their latency).
+template <int DT, int METRIC, int QCH, bool F32ROWS, int G, class Hook>
 __device__ __forceinline__ float batch_dist_xg(const SearchParams &P, const float4 (&qv)[QCH],
                                                int32_t cand, uint64_t mask, int nch, bool mask_tail,
-                                               int32_t *xb) {
+                                               int32_t *xb, Hook &hook) {
     constexpr int DL = F32ROWS ? DT_F32 : DT;
     using Raw = typename RawChunk<DL>::T;
     const int lane = lane_id();
@@ -414,6 +420,7 @@ __device__ __forceinline__ float batch_dist_xg(const SearchParams &P, const floa
                 }
             }
         }
+        if (base == 0) hook();
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             if (base + 2 * g >= cnt) break;
@@ -443,16 +450,16 @@ __device__ __forceinline__ float batch_dist_xg(const SearchParams &P, const floa
     return res;
 }
 
-template <int DT, int METRIC, int QCH, bool F32ROWS = false>
+template <int DT, int METRIC, int QCH, bool F32ROWS = false, class Hook = NoHook>
 __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 (&qv)[QCH],
                                             int32_t cand, uint64_t mask, int nch, bool mask_tail,
-                                            int32_t *xb) {
+                                            int32_t *xb, Hook &&hook = Hook{}) {
     constexpr int GM = dist_rounds_max<F32ROWS ? DT_F32 : DT, QCH>();
     const int cnt = __popcll(mask);
-    if (GM >= 2 && cnt <= 2) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 1>(P, qv, cand, mask, nch, mask_tail, xb);
-    if (GM >= 4 && cnt <= 4) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 2>(P, qv, cand, mask, nch, mask_tail, xb);
-    if (GM >= 8 && cnt <= 8) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 4>(P, qv, cand, mask, nch, mask_tail, xb);
-    return batch_dist_xg<DT, METRIC, QCH, F32ROWS, GM>(P, qv, cand, mask, nch, mask_tail, xb);
+    if (GM >= 2 && cnt <= 2) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 1>(P, qv, cand, mask, nch, mask_tail, xb, hook);
+    if (GM >= 4 && cnt <= 4) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 2>(P, qv, cand, mask, nch, mask_tail, xb, hook);
+    if (GM >= 8 && cnt <= 8) return batch_dist_xg<DT, METRIC, QCH, F32ROWS, 4>(P, qv, cand, mask, nch, mask_tail, xb, hook);
+    return batch_dist_xg<DT, METRIC, QCH, F32ROWS, GM>(P, qv, cand, mask, nch, mask_tail, xb, hook);
 }
 
 // ---------------------------------------------------------------- visited set
@@ -555,21 +562,33 @@ __device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t 
 // complete in issue order, so the wait on those reads does not include it (it
 // is issued in every round so that all paths into the scan wait alike). pfv is
 // not consumed here.
-template <bool PF>
+//
+// With FIRST the first round scans a0/b0, the eight slots at s read earlier
+// (spec_read, after every earlier claim of this wave), instead of reading
+// them: the probe's round trip then overlaps the previous hop's work.
+template <bool PF, bool FIRST = false>
 __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
-                                              bool act, const int32_t *pf, int32_t &pfv) {
+                                              bool act, const int32_t *pf, int32_t &pfv,
+                                              const int4 &a0 = int4{}, const int4 &b0 = int4{}) {
     const int lane = lane_id();
     bool isnew = false, pending = act;
     if (ballot(pending) == 0) {
         if (PF) pfv = *pf;
         return false;
     }
+    bool first = FIRST;
     for (;;) {
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
         // every lane reads (a finished lane its last group, a valid slot)
         const uint32_t g = s & ~3u;
-        const int4 a = *reinterpret_cast<const int4 *>(tab + g);
-        const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
+        int4 a, b;
+        if (first) {
+            a = a0;
+            b = b0;
+        } else {
+            a = *reinterpret_cast<const int4 *>(tab + g);
+            b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
+        }
         if (PF) {
             __asm__ volatile("" ::: "memory");  // keeps the prefetch behind the table reads
             pfv = *pf;
@@ -604,8 +623,19 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
             s = (target + 1u) & msk;  // the slot is taken by a lower lane: probe on
         }
         if (ballot(pending) == 0) break;
+        first = false;
     }
     return isnew;
+}
+
+// The eight workspace-table slots at which the probe of `id` starts (the
+// aligned group of four holding its hash slot and the next group); inactive
+// lanes read group 0.
+__device__ __forceinline__ void spec_read(const Visited &V, int32_t id, bool act, int4 &a, int4 &b) {
+    const uint32_t msk = (uint32_t)V.Hg - 1u;
+    const uint32_t g = act ? (hash_slot(id, V.hgshift) & ~3u) : 0u;
+    a = *reinterpret_cast<const int4 *>(V.gtab + g);
+    b = *reinterpret_cast<const int4 *>(V.gtab + ((g + 4u) & msk));
 }
 
 // Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the
