@@ -233,13 +233,16 @@ deg_status deg_search_batch(const deg_vectors *v, const deg_graph *g, const floa
                             size_t ws_bytes, void *stream);
 
 /*
- * Exact k nearest neighbours (Eq. knn) by brute force on matrix cores.
- * FP32 matrix products (v_mfma_f32_32x32x2f32) of the norm expansion find
- * candidates (exact for integer-valued data below 256); the best k + margin
- * per query are then recomputed as direct FP32 differences in the C32x4 order
- * and sorted by (distance, id). exclude_ids: nullable, one id per query kept
- * out of its result (exploratory ground truth). base rows are read as float4:
- * b_stride must be a multiple of 4.
+ * Exact k nearest neighbours (Eq. knn) by brute force on matrix cores, k <= 1024.
+ * Candidates come from matrix products of the norm expansion: BF16 inputs with
+ * FP32 accumulation (v_mfma_f32_32x32x16_bf16) when every base and query value
+ * is an integer of magnitude <= 255 and dim <= 128 (a device-side check; every
+ * product, sum and candidate distance is then an exact integer, so the result
+ * equals the FP64 definition), FP32 inputs (v_mfma_f32_32x32x2f32) otherwise.
+ * The best k + 32 per query and base slice are then recomputed as direct FP32
+ * differences in the C32x4 order and sorted by (distance, id). exclude_ids:
+ * nullable, one id per query kept out of its result (exploratory ground
+ * truth). base rows are read as float4: b_stride must be a multiple of 4.
  */
 size_t deg_knn_workspace_bytes(int64_t n, int32_t dim, int64_t nq, int32_t k);
 deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t dim, int64_t b_stride,

@@ -1,20 +1,23 @@
 // Exact kNN ground truth (Eq. knn) by brute force on matrix cores.
 //
-// Phase 1 (knn_tile_kernel): a workgroup takes 64 queries and one slice of
-//   the base set. For each tile of 128 base rows it forms the 64 x 128 inner
-//   products with v_mfma_f32_32x32x2f32 (FP32 inputs, FP32 accumulation),
-//   turns them into distances (L2: |q|^2 + |x|^2 - 2 q.x; IP: 1 - q.x) and
-//   appends every (distance, id) key below the query's running threshold to
-//   a per-(query, slice) list in the workspace. When a list is nearly full it
-//   is cut to its KC smallest keys (a 64-step bitwise select) and the
-//   threshold becomes the KC-th key.
-// Phase 2 (knn_final_kernel): one wave per query gathers the slices' lists,
-//   recomputes each candidate as a direct FP32 difference in the fixed C32x4
-//   order (the same arithmetic as the search), and keeps the k smallest keys.
-// On integer data below 256 every product and partial sum is an exact
-// integer below 2^24, so phase 1 already ranks exactly and the result equals
-// the FP64 definition; on float data KC = k + margin candidates absorb the
-// rounding of the norm expansion.
+// knn_tile_kernel: a workgroup (4 waves) takes 128 queries and one slice of the
+//   base set, in tiles of 128 base rows. Each wave forms a 64 x 64 block of
+//   inner products on the matrix cores:
+//     - BF16 inputs (v_mfma_f32_32x32x16_bf16, FP32 accumulation) when every
+//       query and base value is an integer of magnitude <= 255 and the
+//       dimension is <= 129: every product, partial sum and norm-expanded
+//       distance is then an exact integer below 2^24, so the candidates rank
+//       exactly as the FP64 definition;
+//     - FP32 inputs (v_mfma_f32_32x32x2f32) otherwise.
+//   A device-side check decides (each kernel variant returns at once when the
+//   other applies). The distances (L2: |q|^2 + |x|^2 - 2 q.x; IP: 1 - q.x) are
+//   compared with each query row's running threshold in the accumulator
+//   registers; the few that pass are appended to the row's list in the
+//   workspace (LDS counters), and a list that is nearly full is cut to its KC
+//   smallest keys, whose largest distance becomes the row's threshold.
+// knn_final_kernel: one wave per query recomputes every candidate as a direct
+//   FP32 difference in the fixed C32x4 order (the search's arithmetic), selects
+//   the k smallest (distance, id) keys and sorts them (bitonic, in LDS).
 #include <hip/hip_runtime.h>
 
 #include "deg.h"
@@ -23,19 +26,25 @@
 namespace degk {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int KQ = 64;     // queries per workgroup
+constexpr int KQ = 128;    // queries per workgroup
 constexpr int KN = 128;    // base rows per tile
-constexpr int KCH = 32;    // dims per K chunk
+constexpr int KCH = 32;    // dims per K chunk of the FP32 path
 constexpr int KMARGIN = 32;
+constexpr int BF16_MAX_DIM = 128;  // the exact BF16 path (it needs dims <= 129): rows of 128 BF16
+constexpr int BF16_PAD = 128;
+constexpr int BF16_LD = BF16_PAD + 8;  // LDS row pitch: consecutive rows start in different banks
 
 struct KnnParams {
     const float *base;
     const float *queries;
+    const uint16_t *base16;   // BF16 copy of the base rows (exact path), dpad per row
     int64_t n, nq, bstride, qstride;
-    int32_t dim, k, kc, cap, nslices, metric;
+    int32_t dim, dpad, k, kc, cap, nslices, metric;
     const int32_t *exclude;
     const float *bnorm, *qnorm;
+    const int32_t *inexact;   // 0: the BF16 path is exact
     uint64_t *lists;   // nq x nslices x cap
     int32_t *counts;   // nq x nslices
     int32_t *out_ids;
@@ -52,48 +61,76 @@ __global__ void row_norm_kernel(const float *x, int64_t n, int32_t dim, int64_t 
     out[i] = s;
 }
 
+__global__ void flag_reset_kernel(int32_t *f) { *f = 0; }
+
+// Sets *flag when a value of the n x dim rows is not an integer of magnitude
+// <= 255 (NaN included).
+__global__ void exact_check_kernel(const float *x, int64_t n, int32_t dim, int64_t stride,
+                                   int32_t *flag) {
+    const int64_t tot = n * dim;
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const float v = x[(i / dim) * stride + i % dim];
+        bad |= !(v == rintf(v) && fabsf(v) <= 255.0f);
+    }
+    if (__ballot(bad) != 0 && lane_id() == 0) atomicOr(flag, 1);
+}
+
+// BF16 copy of the base rows (exact for the values the BF16 path accepts),
+// dpad elements per row, zero beyond dim; skipped when the data is inexact.
+__global__ void to_bf16_kernel(const float *x, int64_t n, int32_t dim, int64_t stride, int32_t dpad,
+                               uint16_t *out, const int32_t *inexact) {
+    if (*inexact) return;
+    const int64_t tot = n * dpad;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < tot;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = i / dpad;
+        const int c = (int)(i % dpad);
+        const float v = c < dim ? x[r * stride + c] : 0.0f;
+        out[i] = (uint16_t)(__float_as_uint(v) >> 16);  // exact: small integers
+    }
+}
+
 // Cuts the `cnt` distinct keys of `buf` (global, one wave) to the kc smallest:
-// the keys are read once into registers (up to SEL_R per lane), the kc-th
-// smallest is built bit by bit from the top by counting the keys below each
-// candidate prefix, and the kept keys are written back compacted. Returns the
-// kc-th key; `cnt` becomes kc (or stays, if cnt <= kc).
-constexpr int SEL_R = 20;  // covers cap = 2 (k + 32) + 128 for k <= 512
+// the kc-th smallest key is built bit by bit from the top by counting the keys
+// below each candidate prefix (the list is read from memory at each step), and
+// the kept keys are written back compacted. Returns the kc-th key.
 __device__ uint64_t cut_list(uint64_t *buf, int &cnt, int kc) {
     const int lane = lane_id();
-    uint64_t v[SEL_R];
-#pragma unroll
-    for (int r = 0; r < SEL_R; ++r) {
-        const int i = lane + WAVE * r;
-        v[r] = i < cnt ? buf[i] : KEY_MAX;
-    }
     uint64_t ans = 0;
     for (int b = 63; b >= 0; --b) {
         const uint64_t cand = ans | (1ull << b);
         int c = 0;
-#pragma unroll
-        for (int r = 0; r < SEL_R; ++r) c += v[r] < cand ? 1 : 0;
+        for (int i = lane; i < cnt; i += WAVE) c += buf[i] < cand ? 1 : 0;
 #pragma unroll
         for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
         if (c < kc) ans = cand;
     }
     int out = 0;
-#pragma unroll
-    for (int r = 0; r < SEL_R; ++r) {
-        const int i = lane + WAVE * r;
-        const bool keep = i < cnt && v[r] <= ans;
+    for (int base = 0; base < cnt; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < cnt ? buf[i] : KEY_MAX;
+        const bool keep = i < cnt && v <= ans;
         const uint64_t m = ballot(keep);
-        if (keep) buf[out + prefix_in(m)] = v[r];
+        wave_sync();
+        __threadfence_block();
+        if (keep) buf[out + prefix_in(m)] = v;
         out += __popcll(m);
+        __threadfence_block();
     }
     cnt = out;
     return ans;
 }
 
-template <int METRIC>
+// Tile kernel. Wave w computes queries 64 (w >> 1) + [0, 64) against base rows
+// 64 (w & 1) + [0, 64) of the tile as 2 x 2 blocks of 32 x 32; in a block's
+// accumulator, lane l register v holds row 8 (v / 4) + 4 (l / 32) + v % 4 and
+// column l % 32.
+template <int METRIC, bool BF>
 __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
-    __shared__ float QsT[KCH][KQ + 1];
-    __shared__ float BsT[KCH][KN + 1];
-    __shared__ float S[KQ][KN + 1];
+    extern __shared__ __align__(16) unsigned char smem[];
+    if (BF ? (*P.inexact != 0) : (*P.inexact == 0 && P.dim <= BF16_MAX_DIM)) return;
     const int t = threadIdx.x;
     const int w = t >> 6, lane = t & 63;
     const int wq = w >> 1, wn = w & 1;
@@ -102,180 +139,292 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
     const int64_t per = (P.n + P.nslices - 1) / P.nslices;
     const int64_t n0 = (int64_t)slice * per;
     const int64_t n1 = min(P.n, n0 + per);
-    // wave w owns query rows 16w .. 16w+15: lane r < 16 keeps row 16w + r's
-    // list threshold and count in registers
-    uint64_t thr_l = KEY_MAX;
-    int cnt_l = 0;
-    // Staging of one (tile, chunk): the thread's 8 query values (row t % 64,
-    // dims 8 (t / 64) ..) and 16 base values (row t % 128, dims 16 (t / 128) ..)
-    // are read into registers one chunk ahead (while the matrix cores work on
-    // the current one, and across the epilogue), then written to LDS.
-    float4 rq[2], rb[4];
-    auto fetch = [&](int64_t bt, int k0) {
-        {
-            const int r = t & 63, dq = (t >> 6) * 8;
-            const int64_t qi = q0 + r;
-            if (qi < P.nq && k0 + dq + 8 <= P.dim && (P.qstride & 3) == 0) {
-                const float4 *src = reinterpret_cast<const float4 *>(P.queries + qi * P.qstride + k0 + dq);
-                rq[0] = src[0];
-                rq[1] = src[1];
-            } else {
-                float v[8];
+    // LDS: per-row list counters, distance thresholds and excluded ids, then the
+    // operand tiles
+    int32_t *rcnt = reinterpret_cast<int32_t *>(smem);               // KQ
+    float *rthr = reinterpret_cast<float *>(smem + 4 * KQ);          // KQ
+    int32_t *rex = reinterpret_cast<int32_t *>(smem + 8 * KQ);       // KQ
+    unsigned char *tiles = smem + 12 * KQ;
+    for (int i = t; i < KQ; i += 256) {
+        rcnt[i] = 0;
+        rthr[i] = __builtin_inff();
+        rex[i] = (P.exclude && q0 + i < P.nq) ? P.exclude[q0 + i] : -1;
+    }
+    // query norms of the rows this lane's accumulator registers hold
+    float qn[2][16];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int c = k0 + dq + j;
-                    v[j] = (qi < P.nq && c < P.dim) ? P.queries[qi * P.qstride + c] : 0.0f;
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) {
+            const int row = 64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            const int64_t qi = q0 + row;
+            qn[bi][v] = (METRIC == DEG_METRIC_L2 && qi < P.nq) ? P.qnorm[qi] : 0.0f;
+        }
+
+    // ---- operand staging
+    // BF16: each wave keeps the A operands of its 64 queries in registers for the
+    //       whole slice (8 k-steps of 16 dims); the tile's base rows (BF16, 128
+    //       per row) are loaded as 16-byte chunks one tile ahead into LDS.
+    // FP32: chunks of 32 dims, k-major ([k][row + 1]), one chunk ahead.
+    uint16_t *B16 = reinterpret_cast<uint16_t *>(tiles);
+    float *QsT = reinterpret_cast<float *>(tiles);
+    float *BsT = QsT + KCH * (KQ + 1);
+    constexpr int NB16 = (KN * BF16_PAD * 2) / (256 * 16);  // 16-byte chunks per thread (8)
+    constexpr int NCK = BF16_PAD / 8;                         // 16-byte chunks per row
+    uint4 rb16[BF ? NB16 : 1];
+    bf16x8 A16[BF ? 2 : 1][BF ? BF16_PAD / 16 : 1];
+    float4 rq[4], rb[4];
+
+    auto fetch16 = [&](int64_t bt) {
+#pragma unroll
+        for (int j = 0; j < NB16; ++j) {
+            const int idx = t + 256 * j;           // chunk index within the tile
+            const int r = idx / NCK, c = idx % NCK;
+            const int64_t bi = bt + r;
+            rb16[j] = bi < n1 ? reinterpret_cast<const uint4 *>(P.base16 + bi * BF16_PAD)[c]
+                              : make_uint4(0u, 0u, 0u, 0u);
+        }
+    };
+    auto stage16 = [&]() {
+#pragma unroll
+        for (int j = 0; j < NB16; ++j) {
+            const int idx = t + 256 * j;
+            const int r = idx / NCK, c = idx % NCK;
+            *reinterpret_cast<uint4 *>(B16 + r * BF16_LD + 8 * c) = rb16[j];
+        }
+    };
+    auto fetch32 = [&](int64_t bt, int k0) {
+        // queries: row t / 2, dims k0 + 16 (t % 2) .. +16
+        {
+            const int r = t >> 1, dq = (t & 1) * 16;
+            const int64_t qi = q0 + r;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                float v[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c = k0 + dq + 4 * j + e;
+                    v[e] = (qi < P.nq && c < P.dim) ? P.queries[qi * P.qstride + c] : 0.0f;
                 }
-                rq[0] = make_float4(v[0], v[1], v[2], v[3]);
-                rq[1] = make_float4(v[4], v[5], v[6], v[7]);
+                rq[j] = make_float4(v[0], v[1], v[2], v[3]);
             }
         }
         {
-            const int r = t & 127, dq = (t >> 7) * 16;
+            const int r = t >> 1, dq = (t & 1) * 16;
             const int64_t bi = bt + r;
             if (bi < n1 && k0 + dq + 16 <= P.dim) {  // rows are 16-byte aligned (b_stride % 4 == 0)
                 const float4 *src = reinterpret_cast<const float4 *>(P.base + bi * P.bstride + k0 + dq);
 #pragma unroll
-                for (int j4 = 0; j4 < 4; ++j4) rb[j4] = src[j4];
+                for (int j = 0; j < 4; ++j) rb[j] = src[j];
             } else {
-                float v[16];
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const int c = k0 + dq + j;
-                    v[j] = (bi < n1 && c < P.dim) ? P.base[bi * P.bstride + c] : 0.0f;
+                for (int j = 0; j < 4; ++j) {
+                    float v[4];
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int c = k0 + dq + 4 * j + e;
+                        v[e] = (bi < n1 && c < P.dim) ? P.base[bi * P.bstride + c] : 0.0f;
+                    }
+                    rb[j] = make_float4(v[0], v[1], v[2], v[3]);
                 }
-#pragma unroll
-                for (int j4 = 0; j4 < 4; ++j4)
-                    rb[j4] = make_float4(v[4 * j4], v[4 * j4 + 1], v[4 * j4 + 2], v[4 * j4 + 3]);
             }
         }
     };
-    auto stage = [&]() {
-        {
-            const int r = t & 63, dq = (t >> 6) * 8;
-            QsT[dq + 0][r] = rq[0].x; QsT[dq + 1][r] = rq[0].y; QsT[dq + 2][r] = rq[0].z; QsT[dq + 3][r] = rq[0].w;
-            QsT[dq + 4][r] = rq[1].x; QsT[dq + 5][r] = rq[1].y; QsT[dq + 6][r] = rq[1].z; QsT[dq + 7][r] = rq[1].w;
-        }
-        {
-            const int r = t & 127, dq = (t >> 7) * 16;
+    auto stage32 = [&]() {
+        const int r = t >> 1, dq = (t & 1) * 16;
 #pragma unroll
-            for (int j4 = 0; j4 < 4; ++j4) {
-                BsT[dq + 4 * j4 + 0][r] = rb[j4].x;
-                BsT[dq + 4 * j4 + 1][r] = rb[j4].y;
-                BsT[dq + 4 * j4 + 2][r] = rb[j4].z;
-                BsT[dq + 4 * j4 + 3][r] = rb[j4].w;
-            }
+        for (int j = 0; j < 4; ++j) {
+            QsT[(dq + 4 * j + 0) * (KQ + 1) + r] = rq[j].x;
+            QsT[(dq + 4 * j + 1) * (KQ + 1) + r] = rq[j].y;
+            QsT[(dq + 4 * j + 2) * (KQ + 1) + r] = rq[j].z;
+            QsT[(dq + 4 * j + 3) * (KQ + 1) + r] = rq[j].w;
+            BsT[(dq + 4 * j + 0) * (KN + 1) + r] = rb[j].x;
+            BsT[(dq + 4 * j + 1) * (KN + 1) + r] = rb[j].y;
+            BsT[(dq + 4 * j + 2) * (KN + 1) + r] = rb[j].z;
+            BsT[(dq + 4 * j + 3) * (KN + 1) + r] = rb[j].w;
         }
     };
-    if (n0 < n1) fetch(n0, 0);
+
+    if (BF) {
+        // A operands: lane l of block bi, k-step s holds query row 32 bi + l % 32 of
+        // the wave, dims 16 s + 8 (l / 32) .. + 7, as BF16 (exact), zero beyond dim
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+            const int64_t qi = q0 + 64 * wq + 32 * bi + (lane & 31);
+#pragma unroll
+            for (int ks = 0; ks < BF16_PAD / 16; ++ks) {
+                uint32_t wd[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int c0 = 16 * ks + 8 * (lane >> 5) + 2 * e;
+                    const float v0 = (qi < P.nq && c0 < P.dim) ? P.queries[qi * P.qstride + c0] : 0.0f;
+                    const float v1 = (qi < P.nq && c0 + 1 < P.dim) ? P.queries[qi * P.qstride + c0 + 1] : 0.0f;
+                    wd[e] = (__float_as_uint(v0) >> 16) | (__float_as_uint(v1) & 0xffff0000u);
+                }
+                A16[bi][ks] = __builtin_bit_cast(bf16x8, make_uint4(wd[0], wd[1], wd[2], wd[3]));
+            }
+        }
+        if (n0 < n1) fetch16(n0);
+    } else {
+        if (n0 < n1) fetch32(n0, 0);
+    }
+    __syncthreads();
+
     for (int64_t b0 = n0; b0 < n1; b0 += KN) {
-        floatx16 acc0, acc1;
+        floatx16 acc[2][2];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            acc0[v] = 0.0f;
-            acc1[v] = 0.0f;
-        }
-        for (int k0 = 0; k0 < P.dim; k0 += KCH) {
-            stage();
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int v = 0; v < 16; ++v) acc[bi][bj][v] = 0.0f;
+        if (BF) {
+            stage16();
             __syncthreads();
-            // the next chunk of this tile, or the first chunk of the next tile
-            if (k0 + KCH < P.dim)
-                fetch(b0, k0 + KCH);
-            else if (b0 + KN < n1)
-                fetch(b0 + KN, 0);
+            if (b0 + KN < n1) fetch16(b0 + KN);
+            const int g = lane >> 5, c32 = lane & 31;
 #pragma unroll
-            for (int kk = 0; kk < KCH; kk += 2) {
-                int kr = kk + (lane >> 5);
-                float a = QsT[kr][wq * 32 + (lane & 31)];
-                float b0v = BsT[kr][wn * 64 + (lane & 31)];
-                float b1v = BsT[kr][wn * 64 + 32 + (lane & 31)];
-                acc0 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b0v, acc0, 0, 0, 0);
-                acc1 = __builtin_amdgcn_mfma_f32_32x32x2f32(a, b1v, acc1, 0, 0, 0);
+            for (int ks = 0; ks < BF16_PAD / 16; ++ks) {
+                bf16x8 b[2];
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    b[bj] = *reinterpret_cast<const bf16x8 *>(B16 + (64 * wn + 32 * bj + c32) * BF16_LD +
+                                                              16 * ks + 8 * g);
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+                        acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(A16[bi][ks], b[bj],
+                                                                              acc[bi][bj], 0, 0, 0);
             }
-            __syncthreads();
-        }
-        // 32x32 accumulator layout: lane l, register v -> row 8(v/4) + 4(l/32) + v%4, col l%32
+        } else {
+            for (int k0 = 0; k0 < P.dim; k0 += KCH) {
+                stage32();
+                __syncthreads();
+                if (k0 + KCH < P.dim)
+                    fetch32(b0, k0 + KCH);
+                else if (b0 + KN < n1)
+                    fetch32(b0 + KN, 0);
+#pragma unroll 4
+                for (int kk = 0; kk < KCH; kk += 2) {
+                    const int kr = kk + (lane >> 5);
+                    float a[2], b[2];
 #pragma unroll
-        for (int v = 0; v < 16; ++v) {
-            int row = wq * 32 + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
-            int col = wn * 64 + (lane & 31);
-            S[row][col] = acc0[v];
-            S[row][col + 32] = acc1[v];
+                    for (int bi = 0; bi < 2; ++bi) a[bi] = QsT[kr * (KQ + 1) + 64 * wq + 32 * bi + (lane & 31)];
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj) b[bj] = BsT[kr * (KN + 1) + 64 * wn + 32 * bj + (lane & 31)];
+#pragma unroll
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj)
+                            acc[bi][bj] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+                }
+                __syncthreads();
+            }
         }
+
+        // ---- epilogue in the accumulator layout: distance, threshold test, append
+        float bn[2];
+        int64_t cid[2];
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            cid[bj] = b0 + 64 * wn + 32 * bj + (lane & 31);
+            bn[bj] = (METRIC == DEG_METRIC_L2 && cid[bj] < n1) ? P.bnorm[cid[bj]] : 0.0f;
+        }
+        bool any = false;
+        uint32_t passm[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi) {
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) {
+                uint32_t pm = 0;
+#pragma unroll
+                for (int v = 0; v < 16; ++v) {
+                    const int row = 64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    const float dot = acc[bi][bj][v];
+                    float d;
+                    if (METRIC == DEG_METRIC_L2)
+                        d = __fsub_rn(__fadd_rn(qn[bi][v], bn[bj]), __fmul_rn(2.0f, dot));
+                    else
+                        d = __fsub_rn(1.0f, dot);
+                    acc[bi][bj][v] = d;
+                    const bool ok = cid[bj] < n1 && q0 + row < P.nq && d <= rthr[row];
+                    pm |= ok ? (1u << v) : 0u;
+                }
+                passm[bi][bj] = pm;
+                any |= pm != 0;
+            }
+        }
+        if (ballot(any) != 0) {
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+                    for (uint32_t pm = passm[bi][bj]; pm; pm &= pm - 1) {
+                        const int v = __builtin_ctz(pm);
+                        const int row = 64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                        if ((int32_t)cid[bj] == rex[row]) continue;  // kept out of this query's answer
+                        const int pos = atomicAdd(&rcnt[row], 1);
+                        P.lists[((q0 + row) * P.nslices + slice) * P.cap + pos] =
+                            make_key(acc[bi][bj][v], (int32_t)cid[bj]);
+                    }
+        }
+        __threadfence_block();
         __syncthreads();
-        // epilogue: wave w takes query rows 16w .. 16w+15; the base norms of the
-        // tile's columns and the rows' query norms are read once per tile
-        float bn[2] = {0.f, 0.f};
-        if (METRIC == DEG_METRIC_L2) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int64_t bi = b0 + lane + 64 * h;
-                bn[h] = P.bnorm[bi < n1 ? bi : 0];
+        // lists that another tile could overflow are cut to their KC smallest keys
+        for (int rr = 0; rr < KQ / 4; ++rr) {
+            const int row = w * (KQ / 4) + rr;
+            int c = rcnt[row];
+            if (c > P.cap - KN && q0 + row < P.nq) {
+                uint64_t *lst = P.lists + ((q0 + row) * P.nslices + slice) * P.cap;
+                const uint64_t th = cut_list(lst, c, P.kc);
+                if (lane == 0) {
+                    rcnt[row] = c;
+                    rthr[row] = key_dist(th);
+                }
             }
         }
-        const int64_t qrow0 = q0 + w * 16 + (lane & 15);
-        const float qn_l = (METRIC == DEG_METRIC_L2 && qrow0 < P.nq) ? P.qnorm[qrow0] : 0.f;
-        const int32_t ex_l = (P.exclude && qrow0 < P.nq) ? P.exclude[qrow0] : -1;
-        for (int rr = 0; rr < 16; ++rr) {
-            int row = w * 16 + rr;
-            int64_t qi = q0 + row;
-            if (qi >= P.nq) break;
-            const int32_t ex = __builtin_amdgcn_readlane(ex_l, rr);
-            const float qn = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, qn_l), rr));
-            uint64_t th = read_lane_u64(thr_l, rr);
-            uint64_t key[2];
-            bool pass[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                int col = lane + 64 * h;
-                int64_t bi = b0 + col;
-                float dot = S[row][col];
-                float d;
-                if (METRIC == DEG_METRIC_L2)
-                    d = __fsub_rn(__fadd_rn(qn, bn[h]), __fmul_rn(2.0f, dot));
-                else
-                    d = __fsub_rn(1.0f, dot);
-                key[h] = make_key(d, (int32_t)bi);
-                pass[h] = bi < n1 && bi != ex && key[h] < th;
-            }
-            uint64_t *lst = P.lists + ((int64_t)qi * P.nslices + slice) * P.cap;
-            int c = __builtin_amdgcn_readlane(cnt_l, rr);
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                uint64_t m = ballot(pass[h]);
-                if (pass[h]) lst[c + prefix_in(m)] = key[h];
-                c += __popcll(m);
-            }
-            if (c > P.cap - KN) {
-                __threadfence_block();
-                wave_sync();
-                th = cut_list(lst, c, P.kc);
-            }
-            if (lane == rr) {
-                cnt_l = c;
-                thr_l = th;
-            }
-        }
+        __threadfence_block();
         __syncthreads();
     }
-    // final cut to KC
-    for (int rr = 0; rr < 16; ++rr) {
-        int row = w * 16 + rr;
-        int64_t qi = q0 + row;
+    // final cut to KC and the list sizes
+    for (int rr = 0; rr < KQ / 4; ++rr) {
+        const int row = w * (KQ / 4) + rr;
+        const int64_t qi = q0 + row;
         if (qi >= P.nq) break;
-        uint64_t *lst = P.lists + ((int64_t)qi * P.nslices + slice) * P.cap;
-        int c = __builtin_amdgcn_readlane(cnt_l, rr);
-        __threadfence_block();
-        wave_sync();
+        int c = rcnt[row];
+        uint64_t *lst = P.lists + (qi * P.nslices + slice) * P.cap;
         if (c > P.kc) cut_list(lst, c, P.kc);
         if (lane == 0) P.counts[qi * P.nslices + slice] = c;
     }
 }
 
+// Sorts n8 (a power of two, >= 2) keys in LDS ascending (bitonic network, one wave).
+__device__ void bitonic_sort(uint64_t *a, int n8) {
+    const int lane = lane_id();
+    for (int size = 2; size <= n8; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            wave_sync();
+            for (int i = lane; i < n8 / 2; i += WAVE) {
+                const int lo = 2 * i - (i & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint64_t x = a[lo], y = a[hi];
+                if ((x > y) == up) {
+                    a[lo] = y;
+                    a[hi] = x;
+                }
+            }
+            wave_sync();
+        }
+    }
+}
+
 template <int METRIC, int QCH>
-__global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P) {
+__global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P, int p2) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *keys = reinterpret_cast<uint64_t *>(smem);       // nslices * kc
+    uint64_t *top = keys + (size_t)P.nslices * P.kc;            // p2 (power of two >= k)
     const int lane = lane_id(), p = lane & 31;
     const int64_t qi = blockIdx.x;
     if (qi >= P.nq) return;
@@ -308,8 +457,8 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P) {
         }
     }
     wave_sync();
-    // k smallest keys, sorted
-    int kk = min(P.k, tot);
+    // the k smallest keys (the k-th built bit by bit), then sorted
+    const int kk = min(P.k, tot);
     uint64_t kth = KEY_MAX;
     if (tot > kk) {
         uint64_t ans = 0;
@@ -323,31 +472,39 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P) {
         }
         kth = ans;
     }
-    for (int i = lane; i < tot; i += WAVE) {
-        uint64_t v = keys[i];
-        if (v <= kth) {
-            int rank = 0;
-            for (int j = 0; j < tot; ++j) rank += keys[j] < v ? 1 : 0;
-            if (rank < kk) {
-                P.out_ids[qi * P.k + rank] = key_id(v);
-                P.out_dists[qi * P.k + rank] = key_dist(v);
-            }
-        }
+    int out = 0;
+    for (int base = 0; base < tot; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < tot ? keys[i] : KEY_MAX;
+        const bool keep = i < tot && v <= kth;
+        const uint64_t m = ballot(keep);
+        if (keep) top[out + prefix_in(m)] = v;
+        out += __popcll(m);
     }
-    for (int i = kk + lane; i < P.k; i += WAVE) {
-        P.out_ids[qi * P.k + i] = -1;
-        P.out_dists[qi * P.k + i] = __builtin_inff();
+    for (int i = out + lane; i < p2; i += WAVE) top[i] = KEY_MAX;
+    wave_sync();
+    bitonic_sort(top, p2);
+    for (int i = lane; i < P.k; i += WAVE) {
+        const bool have = i < kk;
+        P.out_ids[qi * P.k + i] = have ? key_id(top[i]) : -1;
+        P.out_dists[qi * P.k + i] = have ? key_dist(top[i]) : __builtin_inff();
     }
+}
+
+static int pow2_ge(int x) {
+    int p = 2;
+    while (p < x) p <<= 1;
+    return p;
 }
 
 // Slices of the base set: enough workgroups to fill the chip (about 4 per CU),
 // at least 4 tiles per slice, and the final kernel's candidate keys
-// (slices x KC x 8 bytes) within 60 KiB of LDS.
+// (slices x KC x 8 bytes) plus the sorted top within 60 KiB of LDS.
 static int knn_slices(int64_t n, int64_t nq, int32_t k) {
     int64_t qb = (nq + KQ - 1) / KQ;
     int64_t want = (4 * 256 + qb - 1) / qb;
     int64_t maxs = (n + 4 * KN - 1) / (4 * KN);
-    int64_t maxl = (60 * 1024) / (8 * (int64_t)(k + KMARGIN));
+    int64_t maxl = (60 * 1024 - 8 * (int64_t)pow2_ge(k)) / (8 * (int64_t)(k + KMARGIN));
     if (want > maxs) want = maxs;
     if (want > maxl) want = maxl;
     if (want > 64) want = 64;
@@ -355,17 +512,21 @@ static int knn_slices(int64_t n, int64_t nq, int32_t k) {
     return (int)want;
 }
 
+static int32_t bf16_pad(int32_t dim) { return (dim + 15) / 16 * 16; }
+
 }  // namespace degk
 
 using namespace degk;
 
 extern "C" size_t deg_knn_workspace_bytes(int64_t n, int32_t dim, int64_t nq, int32_t k) {
-    (void)dim;
-    if (n < 1 || nq < 0 || k < 1) return 0;
+    if (n < 1 || nq < 0 || k < 1 || dim < 1) return 0;
     int ns = knn_slices(n, nq, k);
     int64_t kc = k + KMARGIN;
     int64_t cap = 2 * kc + KN;
-    return 256 + (size_t)n * 4 + (size_t)nq * 4 + (size_t)nq * ns * 4 + (size_t)nq * ns * cap * 8;
+    size_t b16 = dim <= BF16_MAX_DIM ? (size_t)n * BF16_PAD * 2 : 0;
+    size_t off = 256 + (size_t)n * 4 + (size_t)nq * 4 + (size_t)nq * ns * 4;
+    off = (off + 255) / 256 * 256 + (b16 + 255) / 256 * 256;
+    return off + (size_t)nq * ns * cap * 8;
 }
 
 extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t dim,
@@ -375,7 +536,7 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
                                          float *out_dists, void *workspace, size_t ws_bytes,
                                          void *stream) {
     if (!base || n < 1 || dim < 1 || b_stride < dim || (b_stride & 3) || nq < 0 || k < 1 ||
-        k > 512 || (metric != DEG_METRIC_L2 && metric != DEG_METRIC_IP))
+        k > 1024 || (metric != DEG_METRIC_L2 && metric != DEG_METRIC_IP))
         return DEG_ERR_INVALID_ARG;
     if (nq > 0 && (!queries || q_stride < dim || !out_ids || !out_dists)) return DEG_ERR_INVALID_ARG;
     if (((dim + 3) / 4 + 31) / 32 > 12 || n > 0x7fffffffLL) return DEG_ERR_UNSUPPORTED;
@@ -391,22 +552,29 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
     P.bstride = b_stride;
     P.qstride = q_stride;
     P.dim = dim;
+    P.dpad = bf16_pad(dim);
     P.k = k;
     P.kc = k + KMARGIN;
     P.cap = 2 * P.kc + KN;
     P.nslices = knn_slices(n, nq, k);
     P.metric = metric;
     P.exclude = exclude_ids;
-    char *ws = reinterpret_cast<char *>(workspace) + 256;
-    float *bn = reinterpret_cast<float *>(ws);
+    char *w = reinterpret_cast<char *>(workspace);
+    int32_t *flag = reinterpret_cast<int32_t *>(w);
+    float *bn = reinterpret_cast<float *>(w + 256);
     float *qn = bn + n;
     int32_t *counts = reinterpret_cast<int32_t *>(qn + nq);
     size_t off = 256 + (size_t)n * 4 + (size_t)nq * 4 + (size_t)nq * P.nslices * 4;
-    off = (off + 7) / 8 * 8;
+    off = (off + 255) / 256 * 256;
+    const bool try16 = dim <= BF16_MAX_DIM;
+    size_t b16 = try16 ? (size_t)n * BF16_PAD * 2 : 0;
+    P.base16 = reinterpret_cast<const uint16_t *>(w + off);
+    off += (b16 + 255) / 256 * 256;
     P.bnorm = bn;
     P.qnorm = qn;
     P.counts = counts;
-    P.lists = reinterpret_cast<uint64_t *>(reinterpret_cast<char *>(workspace) + off);
+    P.inexact = flag;
+    P.lists = reinterpret_cast<uint64_t *>(w + off);
     if (off + (size_t)nq * P.nslices * P.cap * 8 > ws_bytes) return DEG_ERR_WORKSPACE;
     P.out_ids = out_ids;
     P.out_dists = out_dists;
@@ -414,15 +582,29 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
                        dim, b_stride, bn);
     hipLaunchKernelGGL(row_norm_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, st,
                        queries, nq, dim, q_stride, qn);
+    hipLaunchKernelGGL(flag_reset_kernel, dim3(1), dim3(1), 0, st, flag);
     dim3 g1((unsigned)((nq + KQ - 1) / KQ), (unsigned)P.nslices);
-    if (metric == DEG_METRIC_L2)
-        hipLaunchKernelGGL(knn_tile_kernel<DEG_METRIC_L2>, g1, dim3(256), 0, st, P);
-    else
-        hipLaunchKernelGGL(knn_tile_kernel<DEG_METRIC_IP>, g1, dim3(256), 0, st, P);
+    if (try16) {
+        hipLaunchKernelGGL(exact_check_kernel, dim3(2048), dim3(256), 0, st, base, n, dim, b_stride,
+                           flag);
+        hipLaunchKernelGGL(exact_check_kernel, dim3(256), dim3(256), 0, st, queries, nq, dim,
+                           q_stride, flag);
+        hipLaunchKernelGGL(to_bf16_kernel, dim3(4096), dim3(256), 0, st, base, n, dim, b_stride,
+                           BF16_PAD, const_cast<uint16_t *>(P.base16), flag);
+        const size_t lds16 = 12 * KQ + (size_t)KN * BF16_LD * 2;
+        void (*t16)(KnnParams) = metric == DEG_METRIC_L2 ? knn_tile_kernel<DEG_METRIC_L2, true>
+                                                         : knn_tile_kernel<DEG_METRIC_IP, true>;
+        hipLaunchKernelGGL(t16, g1, dim3(256), lds16, st, P);
+    }
+    const size_t lds32 = 12 * KQ + (size_t)KCH * (KQ + 1) * 4 + (size_t)KCH * (KN + 1) * 4;
+    void (*t32)(KnnParams) = metric == DEG_METRIC_L2 ? knn_tile_kernel<DEG_METRIC_L2, false>
+                                                     : knn_tile_kernel<DEG_METRIC_IP, false>;
+    hipLaunchKernelGGL(t32, g1, dim3(256), lds32, st, P);
     int q = ((dim + 3) / 4 + 31) / 32;
     int qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
-    size_t lds = (size_t)P.nslices * P.kc * 8 + WAVE * 4 * 2;
-    void (*fn)(KnnParams) = nullptr;
+    const int p2 = pow2_ge(k);
+    size_t lds = (size_t)P.nslices * P.kc * 8 + (size_t)p2 * 8;
+    void (*fn)(KnnParams, int) = nullptr;
     if (metric == DEG_METRIC_L2)
         fn = qch == 1 ? knn_final_kernel<DEG_METRIC_L2, 1>
                       : (qch == 2 ? knn_final_kernel<DEG_METRIC_L2, 2>
@@ -434,6 +616,6 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
                                   : (qch == 4 ? knn_final_kernel<DEG_METRIC_IP, 4>
                                               : knn_final_kernel<DEG_METRIC_IP, 12>));
     if (lds > 64 * 1024) return DEG_ERR_UNSUPPORTED;
-    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, st, P);
+    hipLaunchKernelGGL(fn, dim3((unsigned)nq), dim3(64), lds, st, P, p2);
     return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
 }

@@ -140,7 +140,11 @@ def test_medoid_matches_oracle(A, kind, metric):
 
 
 # ---------------------------------------------------------------- brute force
-@pytest.mark.parametrize("n,nq,m,k", [(5000, 300, 128, 10), (7000, 130, 24, 100), (3000, 64, 37, 1)])
+# integer data of magnitude <= 255 with at most 128 dims takes the exact BF16 matrix-core
+# path; 129..300 dims (and any non-integer value) the FP32 path: both must equal FP64
+@pytest.mark.parametrize("n,nq,m,k", [(5000, 300, 128, 10), (7000, 130, 24, 100), (3000, 64, 37, 1),
+                                      (9000, 200, 128, 1000), (4100, 257, 130, 1024),
+                                      (6000, 140, 300, 64)])
 def test_knn_integer_exact(A, n, nq, m, k):
     x = synth.small_int(6, n, m, hi=256)
     q = synth.small_int(7, nq, m, hi=256)
@@ -176,6 +180,20 @@ def test_knn_float_tolerance(A, kind, metric, m):
                 j for j in range(6000) if abs(oracle.dist64(x[j], q[i], metric) - rds[i, -1]) <=
                 1e-6 * max(1.0, abs(rds[i, -1]))), i
         assert np.allclose(ds[i], rds[i], rtol=1e-6, atol=1e-6)
+
+
+def test_knn_fp32_path_on_half_integer_queries(A):
+    # one non-integer query value sends every query to the FP32 path; values are
+    # multiples of 1/2 below 128, so FP32 products and sums are still exact
+    x = synth.small_int(11, 5000, 64, hi=128).astype(np.float32)
+    q = synth.small_int(12, 150, 64, hi=128).astype(np.float32)
+    q[3, 5] += 0.5
+    say("knn fp32 path")
+    ids, ds = A.knn_bruteforce(dev(x), dev(q), 50)
+    torch.cuda.synchronize()
+    rids, rds = oracle.knn64(x, q, 50)
+    assert (ids.cpu().numpy() == rids).all()
+    assert (ds.cpu().numpy().astype(np.float64) == rds).all()
 
 
 def test_knn_exclude(A):
