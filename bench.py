@@ -35,7 +35,7 @@ sys.path.insert(0, str(ROOT))
 
 EPS_SWEEP = [0.0, 0.05, 0.1, 0.12, 0.14, 0.15, 0.16, 0.17, 0.18, 0.19, 0.2, 0.22, 0.25, 0.3]
 BL_EPS_STEPS = [0.0, 0.02, 0.04, 0.06]  # eps above the B operating point tried with the stop model
-L_SWEEP = [256, 512, 1024]
+L_SWEEP = [1024, 4096, 16384]
 HBM_PEAK_GBS = 8000.0
 WORKLOADS = {
     "cfg2": dict(desc="1,000,000 x 128 integer Gaussian mixture (1,000 clusters), squared L2, "
@@ -253,6 +253,81 @@ def run_secondary(a):
         "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None},
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_explore(a):
+    """Exploration at k = 1000 on the 1,183,514 x 100 inner-product workload (the
+    protocol of the paper's exploration experiment: 10,000 base vertices, each its
+    own seed and never returned, recall@1000), plus a second step in which the 20
+    vertices already shown are excluded too (per-query exclusion lists).
+    Ground truth: the brute-force kNN on the matrix cores (FP32 path), the second
+    step's from the first 1,020 results. The eps of each precision is the smallest
+    swept with recall@1000 >= target."""
+    import torch
+
+    import synth
+    from paper_2307_10479_amd import api
+    from synth.io import load_graph
+    api.lib()
+    torch.cuda.set_device(0)
+    gp = ROOT / "data" / "cfg3.deg"
+    if not gp.exists():
+        sys.exit("bench: %s missing; build it with `python -m oracle.build_graph --cfg 3`" % gp)
+    adj, metric, _ = load_graph(gp)
+    base, qids = synth.cfg3()
+    nq, k, shown = len(qids), 1000, 20
+    n, d = adj.shape
+    m = base.shape[1]
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    xb = dev(base)
+    G = api.DeviceGraph(dev(adj))
+    QI = dev(qids)
+    t0 = time.time()
+    gt_ids = np.empty((nq, k + shown), np.int32)
+    for s0 in range(0, nq, 2000):
+        part = QI[s0:s0 + 2000]
+        g_ids, _ = api.knn_bruteforce(xb, xb[part.long()].contiguous(), k + shown, metric,
+                                      exclude=part)
+        gt_ids[s0:s0 + 2000] = g_ids.cpu().numpy()
+    log("exploration ground truth (k=%d) in %.1fs" % (k + shown, time.time() - t0))
+    first_lists = [row[:shown].tolist() for row in gt_ids]
+    excl = api.exclusion_lists(first_lists)
+    gt1, gt2 = gt_ids[:, :k], gt_ids[:, shown:shown + k]
+
+    def rec(ids, gt):
+        return float(np.mean([len(set(x.tolist()) & set(y.tolist())) / k for x, y in zip(ids, gt)]))
+
+    out_rows = {}
+    for dt in ("f32", "bf16"):
+        store = api.VectorStore(xb, dt, metric)
+        for step, ex, gt in (("self", None, gt1), ("shown20", excl, gt2)):
+            rows = []
+            for eps in (0.0, 0.02, 0.05, 0.08, 0.1, 0.12, 0.15, 0.2):
+                fn = lambda e=eps: api.search_indexed(store, G, QI, k, e, exclude=ex)
+                times, (ids, ds, st) = _timed_runs(torch, fn, 1, 3)
+                ms = float(np.median(times))
+                r = rec(ids.cpu().numpy(), gt)
+                stn = st.cpu().numpy()
+                rows.append(dict(eps=eps, recall_at_1000=round(r, 5), ms=round(ms, 3),
+                                 qps=round(nq / (ms / 1e3), 1), hops=round(float(stn[:, 0].mean()), 1),
+                                 evals=round(float(stn[:, 1].mean()), 1)))
+                log("explore %-4s %-7s eps %.2f recall@1000 %.4f %.2f ms %.0f QPS hops %.0f"
+                    % (dt, step, eps, r, ms, nq / (ms / 1e3), stn[:, 0].mean()))
+                if r >= a.recall:
+                    break
+            out_rows["%s_%s" % (dt, step)] = rows
+    head = out_rows["bf16_self"][-1]
+    out = {
+        "metric": "QPS @ recall@1000>=%.2f, exploration (cfg3)" % a.recall,
+        "value": head["qps"], "unit": "queries/s", "n_gpus": 1, "steps": 3, "warmup": 1,
+        "ms_per_step": head["ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "cfg3 exploration: %s" % WORKLOADS["cfg3"]["desc"].replace("k=100", "k=1000"),
+                   "k": k, "shown_excluded": shown, "sweeps": out_rows},
+        "roofline": None, "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
     return 0
@@ -509,6 +584,8 @@ def main(argv=None):
                     help="write the operating points, launch tuning and stop model to this .npz")
     ap.add_argument("--profile", default="",
                     help="profile mode: load a --save-state file and run only the timed steps")
+    ap.add_argument("--explore", action="store_true",
+                    help="exploration at k = 1000 (cfg3), with and without shown vertices excluded")
     ap.add_argument("--knn", action="store_true",
                     help="time the brute-force ground truth (matrix cores) instead of the search")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -521,6 +598,8 @@ def main(argv=None):
 
     if a.knn:
         return run_knn(a)
+    if a.explore:
+        return run_explore(a)
     if a.workload in ("cfg3", "cfg4"):
         return run_secondary(a)
     if a.workload == "cfg5":
@@ -785,10 +864,12 @@ def main(argv=None):
         # operating points where no query drops a live candidate: exactly Algorithm 1
         free = {}
         for name, op in (("P", opP), ("B", opB)):
-            for L in sorted(set([op["L"]] + [2 * op["L"], 4 * op["L"]])):
-                if L > 8192:
-                    break
-                rr = report(name, dict(op, L=L), None, steps=5)
+            for L in sorted(set([op["L"], 2 * op["L"], 4 * op["L"], 8 * op["L"], 16384])):
+                try:
+                    rr = report(name, dict(op, L=L), None, steps=5)
+                except api.DegError as e:  # a capacity the launch cannot hold
+                    log("%s at L %d: %s" % (name, L, e))
+                    continue
                 if rr["flags"]["overflow"] == 0.0:
                     free[name] = rr
                     break

@@ -130,7 +130,8 @@ typedef struct {
                            the same as evicting the (distance, id)-largest entry at every
                            push into a full S. DEG_FLAG_QUEUE_OVERFLOW marks a query that
                            lost an entry within r(1+eps) (without it the result is Algorithm
-                           1's exactly); 0 = default min(4096, max(256, 8 k_pool)) */
+                           1's exactly); 0 = default 16384, at most 2^24 (the workspace
+                           holds L + 256 keys per resident wave) */
     int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = the tuned
                            value if one is registered, else 512. At 3/4 load the set moves
                            to a workspace table, and from there to one four times larger
@@ -143,6 +144,15 @@ typedef struct {
     int64_t trace_rows_per_query; /* rows per query in `trace` (each 20 floats) */
     int32_t trace_interval;       /* hops between two trace rows */
     int32_t waves_per_cu;         /* resident waves per CU of the persistent grid; 0 = tuned */
+    int32_t queue_lds;  /* keys of S held in LDS beyond the 64 in registers (multiple of 64,
+                           256..8192; 0 = 512); the farthest keys live in the workspace */
+    /* Exclusion lists (Sec. 4: the exploratory task keeps vertices out of the result):
+     * query i (row, vertex or descriptor i) never returns the ids
+     * exclude_ids[exclude_offsets[i] .. exclude_offsets[i+1]); they are still checked,
+     * enter S and are expanded. Both device pointers or both NULL; ids outside [0, n)
+     * set DEG_FLAG_BAD_ID. An exploratory query also excludes its own vertex. */
+    const int64_t *exclude_offsets;
+    const int32_t *exclude_ids;
 } deg_search_opts;
 
 /*

@@ -60,7 +60,8 @@ class DegSearchOpts(C.Structure):
     _fields_ = [("queue_cap", C.c_int32), ("hash_slots", C.c_int32), ("k_pool", C.c_int32),
                 ("rerank", C.c_int32), ("stop", C.POINTER(DegStopModel)), ("trace", C.c_void_p),
                 ("trace_rows_per_query", C.c_int64), ("trace_interval", C.c_int32),
-                ("waves_per_cu", C.c_int32)]
+                ("waves_per_cu", C.c_int32), ("queue_lds", C.c_int32),
+                ("exclude_offsets", C.c_void_p), ("exclude_ids", C.c_void_p)]
 
 
 class DegQueryDesc(C.Structure):
@@ -268,7 +269,7 @@ class StopModel:
 
 
 def _opts(queue_cap=0, hash_slots=0, k_pool=0, rerank=False, stop: StopModel | None = None,
-          trace=None, trace_rows=0, trace_interval=0, waves_per_cu=0):
+          trace=None, trace_rows=0, trace_interval=0, waves_per_cu=0, queue_lds=0, exclude=None):
     o = DegSearchOpts()
     o.queue_cap, o.hash_slots, o.k_pool, o.rerank = int(queue_cap), int(hash_slots), int(k_pool), int(bool(rerank))
     keep = None
@@ -280,7 +281,20 @@ def _opts(queue_cap=0, hash_slots=0, k_pool=0, rerank=False, stop: StopModel | N
         o.trace_rows_per_query = int(trace_rows)
         o.trace_interval = int(trace_interval)
     o.waves_per_cu = int(waves_per_cu)
+    o.queue_lds = int(queue_lds)
+    if exclude is not None:  # (offsets int64 [nq + 1], ids int32) device tensors
+        o.exclude_offsets = exclude[0].data_ptr()
+        o.exclude_ids = exclude[1].data_ptr()
     return o, keep
+
+
+def exclusion_lists(lists) -> tuple:
+    """Device CSR form of per-query exclusion lists (a sequence of id sequences)."""
+    import numpy as np
+    off = np.zeros(len(lists) + 1, np.int64)
+    off[1:] = np.cumsum([len(x) for x in lists])
+    ids = np.array([v for x in lists for v in x] or [0], np.int32)
+    return torch.from_numpy(off).cuda(), torch.from_numpy(ids).cuda()
 
 
 # ------------------------------------------------------------------ search

@@ -186,7 +186,7 @@ __global__ void __launch_bounds__(64) mlp_forward_bf16_kernel(const uint16_t *W,
     for (int64_t row = blockIdx.x; row < B; row += gridDim.x) {
         const int lane = (int)threadIdx.x & 63;
         const float fs = lane < MLP_IN ? X[row * MLP_IN + lane] : 0.0f;
-        float z = mlp_logit(M, fs, hbuf);
+        float z = mlp_logit(M, W, fs, hbuf);
         if (threadIdx.x == 0) out[row] = z;
     }
 }

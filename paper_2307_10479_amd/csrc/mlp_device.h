@@ -32,12 +32,12 @@ __device__ __forceinline__ float bf16_round(float x) { return __uint_as_float(bf
 __device__ __forceinline__ float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ __forceinline__ float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
 
-// The weights lane j needs (row j of W1 and W2 as BF16 pairs, b1[j], b2[j],
-// w3[j], b3) in registers: 40 words and 4 floats per lane, read with ten
-// 16-byte loads and four 2-byte loads.
+// The first-layer weights lane j needs (row j of W1 as BF16 pairs, b1[j],
+// b2[j], w3[j], b3): 8 words and 4 floats, read with two 16-byte loads and four
+// 2-byte loads. The second layer's row (32 words) is read in chunks while it
+// is used, so that few registers are held at once.
 struct MlpRegs {
     uint32_t w1[8];
-    uint32_t w2[32];
     float b1, b2, w3, b3;
 };
 
@@ -45,16 +45,10 @@ __device__ __forceinline__ MlpRegs mlp_load(const uint16_t *W) {
     const int j = (int)threadIdx.x & 63;
     MlpRegs M;
     const uint4 *w1 = reinterpret_cast<const uint4 *>(W + OFF_W1 + j * MLP_IN);
-    const uint4 *w2 = reinterpret_cast<const uint4 *>(W + OFF_W2 + j * MLP_H);
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
         const uint4 u = w1[t];
         M.w1[4 * t] = u.x; M.w1[4 * t + 1] = u.y; M.w1[4 * t + 2] = u.z; M.w1[4 * t + 3] = u.w;
-    }
-#pragma unroll
-    for (int t = 0; t < 8; ++t) {
-        const uint4 u = w2[t];
-        M.w2[4 * t] = u.x; M.w2[4 * t + 1] = u.y; M.w2[4 * t + 2] = u.z; M.w2[4 * t + 3] = u.w;
     }
     M.b1 = bf16_val(W[OFF_B1 + j]);
     M.b2 = bf16_val(W[OFF_B2 + j]);
@@ -69,8 +63,8 @@ __device__ __forceinline__ MlpRegs mlp_load(const uint16_t *W) {
 // halving tree p_j += p_(j+w) for w = 32, 16, 8, 4, 2, 1; logit = p_0 + b3.
 // relu(s) = s for s > 0, else +0. Every lane returns the same value. Lane
 // t < 16 holds standardised feature t in `fs`. hbuf: 64 floats of LDS owned
-// by the wave, 16-byte aligned.
-__device__ __forceinline__ float mlp_logit(const MlpRegs &M, float fs, float *hbuf) {
+// by the wave, 16-byte aligned. W: the BF16 weights (device).
+__device__ __forceinline__ float mlp_logit(const MlpRegs &M, const uint16_t *W, float fs, float *hbuf) {
     const int j = (int)threadIdx.x & 63;
     const float xb = bf16_round(fs);
     float s = M.b1;
@@ -85,14 +79,22 @@ __device__ __forceinline__ float mlp_logit(const MlpRegs &M, float fs, float *hb
     __builtin_amdgcn_wave_barrier();
     __asm__ volatile("" ::: "memory");
     const float4 *h4 = reinterpret_cast<const float4 *>(hbuf);
+    const uint4 *w2 = reinterpret_cast<const uint4 *>(W + OFF_W2 + j * MLP_H);
     s = M.b2;
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const float4 h = h4[t];
-        s = __fmaf_rn(bf16_lo(M.w2[2 * t]), h.x, s);
-        s = __fmaf_rn(bf16_hi(M.w2[2 * t]), h.y, s);
-        s = __fmaf_rn(bf16_lo(M.w2[2 * t + 1]), h.z, s);
-        s = __fmaf_rn(bf16_hi(M.w2[2 * t + 1]), h.w, s);
+    uint4 wc = w2[0];  // 8 weights per chunk, the next chunk requested before this one is used
+#pragma unroll 1
+    for (int c = 0; c < 8; ++c) {
+        const uint4 wn = c < 7 ? w2[c + 1] : wc;
+        const float4 ha = h4[2 * c], hb = h4[2 * c + 1];
+        s = __fmaf_rn(bf16_lo(wc.x), ha.x, s);
+        s = __fmaf_rn(bf16_hi(wc.x), ha.y, s);
+        s = __fmaf_rn(bf16_lo(wc.y), ha.z, s);
+        s = __fmaf_rn(bf16_hi(wc.y), ha.w, s);
+        s = __fmaf_rn(bf16_lo(wc.z), hb.x, s);
+        s = __fmaf_rn(bf16_hi(wc.z), hb.y, s);
+        s = __fmaf_rn(bf16_lo(wc.w), hb.z, s);
+        s = __fmaf_rn(bf16_hi(wc.w), hb.w, s);
+        wc = wn;
     }
     const float h2 = s > 0.0f ? s : 0.0f;
     float z = __fmul_rn(M.w3, h2);

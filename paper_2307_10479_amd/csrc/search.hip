@@ -24,6 +24,10 @@ __global__ void reset_kernel(int32_t *counter, int32_t *owners, int npool) {
 // region goes up to 131072 slots (512 KiB), and larger sets take one of up
 // to 64 shared tables sized for all n vertices.
 constexpr int HG_FIRST = 8192;
+// S: capacity 16384 by default (at these sizes no search holds that many live
+// candidates, so the result is Algorithm 1's exactly), 512 keys of it in LDS.
+constexpr int DEFAULT_L = 16384;
+constexpr int DEFAULT_BCAP = 512;
 constexpr int HG_PRIV_MAX = 131072;
 constexpr int POOL_MAX = 64;
 
@@ -37,12 +41,13 @@ static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, bool feat) {
 
 struct LaunchCfg {
     KernelFn fn;
-    int H, hshift, L, scap, rreg, qch;
+    int H, hshift, L, bcap, scap, rreg, qch;
+    int64_t gcap;  // far part of S per wave (keys)
     int hg0, hg_priv, hg_cap, npool;
     int64_t region;  // slots per wave
     size_t lds;
     int grid;
-    size_t off_region, off_pool, ws_bytes;
+    size_t off_region, off_pool, off_g, ws_bytes;
 };
 
 static int64_t pow2_at_least(int64_t x) {
@@ -72,7 +77,8 @@ static void size_tables(LaunchCfg &c, int64_t n, int priv_max, int pool_max) {
     c.npool = t < c.hg_cap ? (c.grid < pool_max ? c.grid : pool_max) : 0;
     c.off_region = 256 + ((size_t)4 * c.npool + 255) / 256 * 256;
     c.off_pool = c.off_region + (size_t)c.grid * (size_t)region * 4;
-    c.ws_bytes = c.off_pool + (size_t)c.npool * (size_t)c.hg_cap * 4;
+    c.off_g = c.off_pool + (size_t)c.npool * (size_t)c.hg_cap * 4;
+    c.ws_bytes = c.off_g + (size_t)c.grid * (size_t)c.gcap * 8;
 }
 
 static int ilog2(int x) {
@@ -100,7 +106,9 @@ static deg_status validate_common(const deg_vectors *v, const deg_graph *g, int3
     bool rerank = v->dtype != DEG_F32 || (o && (o->rerank || o->k_pool > kmax));
     if ((rerank || need_f32) && !v->f32_data) return DEG_ERR_INVALID_ARG;
     if (v->f32_data && (v->f32_stride < v->dim || (v->f32_stride & 3))) return DEG_ERR_INVALID_ARG;
-    if (o && o->queue_cap < 0) return DEG_ERR_INVALID_ARG;
+    if (o && (o->queue_cap < 0 || o->queue_cap > (1 << 24))) return DEG_ERR_INVALID_ARG;
+    if (o && o->queue_lds && (o->queue_lds < 256 || o->queue_lds > 8192 || (o->queue_lds & 63)))
+        return DEG_ERR_INVALID_ARG;
     if (o && o->hash_slots && (o->hash_slots < 256 || o->hash_slots > 16384 ||
                                (o->hash_slots & (o->hash_slots - 1))))
         return DEG_ERR_INVALID_ARG;
@@ -110,6 +118,8 @@ static deg_status validate_common(const deg_vectors *v, const deg_graph *g, int3
             return DEG_ERR_INVALID_ARG;
     }
     if (o && o->trace && (o->trace_rows_per_query < 1 || o->trace_interval < 1))
+        return DEG_ERR_INVALID_ARG;
+    if (o && ((o->exclude_offsets == nullptr) != (o->exclude_ids == nullptr)))
         return DEG_ERR_INVALID_ARG;
     return DEG_OK;
 }
@@ -123,10 +133,11 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     int nch = (v->dim + 3) / 4;
     int q = (nch + 31) / 32;
     c.qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
-    int L = (o && o->queue_cap > 0) ? o->queue_cap
-                                    : (8 * kp > 4096 ? 4096 : (8 * kp > 256 ? 8 * kp : 256));
+    int L = (o && o->queue_cap > 0) ? o->queue_cap : DEFAULT_L;
     c.L = L;
-    c.scap = ((L + 64 > kp ? L + 64 : kp) + 63) / 64 * 64;  // B (L - 1 + a row) / rerank buffer
+    c.bcap = (o && o->queue_lds) ? o->queue_lds : DEFAULT_BCAP;
+    c.scap = ((c.bcap > kp ? c.bcap : kp) + 63) / 64 * 64;  // B / rerank buffer
+    c.gcap = (int64_t)L + 4 * 64;  // S never holds more than L + a row at the end of a push
     const TuneEntry *t = tune_lookup(v->dtype, v->dim, g->degree, kp);
     // untuned default: a small LDS table and more resident waves (the workspace
     // table takes over at 3/4 load; measured best or near-best on every workload)
@@ -160,8 +171,11 @@ static deg_status launch(const LaunchCfg &c, SearchParams &P, void *ws, size_t w
     P.pool_owner = reinterpret_cast<int32_t *>(w + 256);
     P.spill = reinterpret_cast<int32_t *>(w + c.off_region);
     P.pool = reinterpret_cast<int32_t *>(w + c.off_pool);
+    P.gspace = reinterpret_cast<uint64_t *>(w + c.off_g);
     P.L = c.L;
+    P.bcap = c.bcap;
     P.scap = c.scap;
+    P.gcap = c.gcap;
     P.H = c.H;
     P.hshift = c.hshift;
     P.hg0 = c.hg0;
@@ -203,6 +217,10 @@ static void fill_common(SearchParams &P, const deg_vectors *v, const deg_graph *
         P.stop_interval = o->stop->interval;
         P.stop_long_hops = o->stop->long_hops > 0 ? o->stop->long_hops : 0x7fffffff;
         P.stop_tau_long = o->stop->long_hops > 0 ? logit(o->stop->tau_long) : P.stop_tau;
+    }
+    if (o) {
+        P.ex_off = o->exclude_offsets;
+        P.ex_ids = o->exclude_ids;
     }
     if (o && o->trace) {
         P.trace = o->trace;
@@ -341,7 +359,7 @@ static bool fit_noalloc(LaunchCfg &c, int64_t n) {
         size_tables(c, n, 0, pool_max);
         if (c.ws_bytes <= NOALLOC_BYTES) return true;
         const size_t fixed = c.off_region + (size_t)c.npool * (size_t)c.hg_cap * 4;
-        const size_t per_wave = (size_t)c.region * 4;
+        const size_t per_wave = (size_t)c.region * 4 + (size_t)c.gcap * 8;
         if (fixed + per_wave <= NOALLOC_BYTES) {
             size_t g = (NOALLOC_BYTES - fixed) / per_wave;
             c.grid = (int)(g < (size_t)grid0 ? g : (size_t)grid0);

@@ -11,23 +11,29 @@
 namespace degk {
 
 // ---------------------------------------------------------------- S (candidates)
-// S is split in two. F, the smallest keys (up to 64), is kept sorted in
-// registers, lane i holding F[i]: a pop reads lane 0 and shifts the wave by one
-// lane. B, all other keys, is an unsorted array in LDS; every key of B is
-// >= beta and every key of F is < beta. New keys below beta are rank-merged
-// into F (the overflow beyond 64 moves to B and lowers beta), the others are
-// appended to B. When F runs empty it is refilled with the 64 smallest live
-// keys of B, found by an exact histogram select. Capacity L: at the end of a
-// hop, if S holds more than L keys, the dead ones are dropped and, if more
-// than L live keys remain, only the L smallest stay. This keeps the same live
-// keys as evicting the largest key at every push into a full S: dead keys are
-// larger than every live one and are never expanded.
+// S is kept in three parts ordered by key: F < B < G. F, the smallest keys (up
+// to 64), is sorted in registers, lane i holding F[i]: a pop reads lane 0 and
+// shifts the wave by one lane. B is an unsorted LDS array (capacity bcap) of
+// keys in [beta, phi); G, the farthest keys (>= phi), is an unsorted array in
+// the wave's workspace region. New keys below beta are rank-merged into F (the
+// overflow beyond 64 moves to B and lowers beta); the others are appended to
+// B or, from phi on, to G. When B is nearly full its dead keys are dropped and
+// its larger half moves to G (phi drops to the median). When F runs empty it is
+// refilled with the 64 smallest live keys of B, found by an exact histogram
+// select; when B runs empty it takes back the smallest live keys of G.
+// Capacity L: at the end of a hop, if S holds more than L keys, the dead ones
+// are dropped and, if more than L live keys remain, only the L smallest stay.
+// This keeps the same live keys as evicting the largest key at every push into
+// a full S: dead keys are larger than every live one and are never expanded.
 struct SQueue {
     uint64_t f;        // per lane: F[lane], KEY_MAX beyond fcnt
     int fcnt;          // wave-uniform
-    uint64_t beta;     // wave-uniform
+    uint64_t beta;     // wave-uniform: every key of B and G is >= beta > every key of F
     uint64_t *B;       // LDS
-    int bcnt;          // wave-uniform
+    int bcnt, bcap;    // wave-uniform
+    uint64_t phi;      // wave-uniform: every key of G is >= phi > every key of B
+    uint64_t *G;       // workspace
+    int gcnt;          // wave-uniform
     uint64_t *stage;   // LDS, 128 keys
     uint32_t *hist;    // LDS, 64 counters
 };
@@ -40,7 +46,8 @@ __device__ __forceinline__ uint64_t lane_shift_down1(uint64_t v) {
     return lane_id() == WAVE - 1 ? KEY_MAX : r;
 }
 
-// In-place forward compaction of B keeping keys with distance <= thr.
+// In-place forward compaction of an array of this wave (LDS or its workspace)
+// keeping keys with distance <= thr.
 __device__ __forceinline__ int b_drop_dead(uint64_t *B, int n, float thr) {
     const int lane = lane_id();
     const uint32_t othr = ord_of(thr);
@@ -58,10 +65,36 @@ __device__ __forceinline__ int b_drop_dead(uint64_t *B, int n, float thr) {
     return out;
 }
 
-// The k-th smallest (1 <= k <= n) of the n distinct keys in B: each round
-// splits the current key range into 64 power-of-two buckets, counts them with
-// LDS atomics and keeps the bucket that holds rank k; at most 64 keys are
-// finally ranked directly.
+// The same for G, in the wave's workspace: four chunks of 64 keys are loaded
+// before any is written back (the writes only go to positions already read),
+// so that the loads of a round overlap instead of waiting one by one.
+__device__ __forceinline__ int g_drop_dead(uint64_t *G, int n, float thr) {
+    const int lane = lane_id();
+    const uint32_t othr = ord_of(thr);
+    int out = 0;
+    for (int base = 0; base < n; base += 4 * WAVE) {
+        uint64_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * WAVE + lane;
+            v[u] = i < n ? G[i] : KEY_MAX;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = base + u * WAVE + lane;
+            const bool keep = i < n && (uint32_t)(v[u] >> 32) <= othr;
+            const uint64_t m = ballot(keep);
+            if (keep) G[out + prefix_in(m)] = v[u];
+            out += __popcll(m);
+        }
+    }
+    return out;
+}
+
+// The k-th smallest (1 <= k <= n) of the n distinct keys in B (LDS or this
+// wave's workspace): each round splits the current key range into 64
+// power-of-two buckets, counts them with LDS atomics and keeps the bucket that
+// holds rank k; at most 64 keys are finally ranked directly.
 __device__ uint64_t b_kth(const uint64_t *B, int n, int k, uint64_t *stage, uint32_t *hist) {
     const int lane = lane_id();
     uint64_t mn = KEY_MAX, mx = 0;
@@ -119,6 +152,27 @@ __device__ uint64_t b_kth(const uint64_t *B, int n, int k, uint64_t *stage, uint
     }
 }
 
+// Moves the keys of `src` (n keys) that are > T to the end of `dst` (which
+// holds *dn keys) and compacts the others in place; returns how many stay.
+__device__ __forceinline__ int split_above(uint64_t *src, int n, uint64_t T, uint64_t *dst, int &dn) {
+    const int lane = lane_id();
+    int out = 0;
+    for (int base = 0; base < n; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < n ? src[i] : KEY_MAX;
+        const bool stay = i < n && v <= T;
+        const bool move = i < n && v > T;
+        const uint64_t ms = ballot(stay), mm = ballot(move);
+        wave_sync();
+        if (stay) src[out + prefix_in(ms)] = v;
+        if (move) dst[dn + prefix_in(mm)] = v;
+        out += __popcll(ms);
+        dn += __popcll(mm);
+        wave_sync();
+    }
+    return out;
+}
+
 // Rank-sorts the c <= 64 keys in stage[0..c) into F.
 __device__ __forceinline__ void f_from_stage(SQueue &S, int c) {
     const int lane = lane_id();
@@ -133,14 +187,69 @@ __device__ __forceinline__ void f_from_stage(SQueue &S, int c) {
     wave_sync();
 }
 
-// F is empty: move the (up to) 64 smallest live keys of B into F.
+// B is empty: it takes back the smallest live keys of G (up to half its capacity;
+// usually most keys of G are dead by then and all live ones fit).
+__device__ void b_from_g(SQueue &S, float thr) {
+    S.gcnt = g_drop_dead(S.G, S.gcnt, thr);
+    if (S.gcnt == 0) {
+        S.phi = KEY_MAX;
+        return;
+    }
+    const int want = S.bcap / 2;
+    if (S.gcnt <= want) {
+        const int lane = lane_id();
+        for (int base = 0; base < S.gcnt; base += 4 * WAVE) {
+            uint64_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = base + u * WAVE + lane;
+                v[u] = i < S.gcnt ? S.G[i] : KEY_MAX;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = base + u * WAVE + lane;
+                if (i < S.gcnt) S.B[i] = v[u];
+            }
+        }
+        wave_sync();
+        S.bcnt = S.gcnt;
+        S.gcnt = 0;
+        S.phi = KEY_MAX;
+        return;
+    }
+    const uint64_t T = S.gcnt <= want ? KEY_MAX : b_kth(S.G, S.gcnt, want, S.stage, S.hist);
+    // keys <= T go to B, the rest stay in G
+    int moved = 0;
+    const int lane = lane_id();
+    int out = 0;
+    for (int base = 0; base < S.gcnt; base += WAVE) {
+        const int i = base + lane;
+        const uint64_t v = i < S.gcnt ? S.G[i] : KEY_MAX;
+        const bool take = i < S.gcnt && v <= T;
+        const bool stay = i < S.gcnt && v > T;
+        const uint64_t mt = ballot(take), ms = ballot(stay);
+        wave_sync();
+        if (take) S.B[moved + prefix_in(mt)] = v;
+        if (stay) S.G[out + prefix_in(ms)] = v;
+        moved += __popcll(mt);
+        out += __popcll(ms);
+        wave_sync();
+    }
+    S.bcnt = moved;
+    S.gcnt = out;
+    S.phi = out > 0 ? T + 1ull : KEY_MAX;
+}
+
+// F is empty: move the (up to) 64 smallest live keys of B (refilled from G when
+// it is empty) into F.
 __device__ void s_refill(SQueue &S, float thr) {
     const int lane = lane_id();
     S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
+    if (S.bcnt == 0 && S.gcnt > 0) b_from_g(S, thr);
     const int n = S.bcnt;
     if (n == 0) {
         S.fcnt = 0;
-        S.beta = KEY_MAX;
+        S.beta = S.gcnt > 0 ? S.phi : KEY_MAX;
         return;
     }
     const uint64_t T = n <= WAVE ? KEY_MAX : b_kth(S.B, n, WAVE, S.stage, S.hist);
@@ -159,14 +268,14 @@ __device__ void s_refill(SQueue &S, float thr) {
         wave_sync();
     }
     S.bcnt = out;
-    S.beta = out > 0 ? T + 1ull : KEY_MAX;
+    S.beta = out > 0 ? T + 1ull : (S.gcnt > 0 ? S.phi : KEY_MAX);
     f_from_stage(S, c);
 }
 
 // Pops the smallest key if it lies within thr; false ends the search.
 __device__ __forceinline__ bool s_pop(SQueue &S, float thr, uint64_t &key) {
     if (S.fcnt == 0) {
-        if (S.bcnt == 0) return false;
+        if (S.bcnt == 0 && S.gcnt == 0) return false;
         s_refill(S, thr);
         if (S.fcnt == 0) return false;
     }
@@ -177,14 +286,29 @@ __device__ __forceinline__ bool s_pop(SQueue &S, float thr, uint64_t &key) {
     return true;
 }
 
-// Adds the keys of the lanes in pm.
-__device__ __forceinline__ void s_push(SQueue &S, uint64_t ck, uint64_t pm) {
+// B keeps room for one hop (a row's keys plus F's overflow): when it is nearly
+// full its dead keys are dropped and, if still needed, its larger half moves to G.
+__device__ __forceinline__ void b_make_room(SQueue &S, float thr) {
+    if (S.bcnt <= S.bcap - 2 * WAVE) return;
+    S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
+    if (S.bcnt <= S.bcap / 2) return;
+    const uint64_t T = b_kth(S.B, S.bcnt, S.bcnt / 2, S.stage, S.hist);
+    S.bcnt = split_above(S.B, S.bcnt, T, S.G, S.gcnt);
+    S.phi = T + 1ull;
+}
+
+// Adds the keys of the lanes in pm (all within the threshold thr).
+__device__ __forceinline__ void s_push(SQueue &S, uint64_t ck, uint64_t pm, float thr) {
     const int lane = lane_id();
     const uint64_t sm = pm & ballot(ck < S.beta);
     const uint64_t bg = pm & ~sm;
     if (bg) {
-        if ((bg >> lane) & 1ull) S.B[S.bcnt + prefix_in(bg)] = ck;
-        S.bcnt += __popcll(bg);
+        const uint64_t bb = bg & ballot(ck < S.phi);
+        const uint64_t gg = bg & ~bb;
+        if ((bb >> lane) & 1ull) S.B[S.bcnt + prefix_in(bb)] = ck;
+        if ((gg >> lane) & 1ull) S.G[S.gcnt + prefix_in(gg)] = ck;
+        S.bcnt += __popcll(bb);
+        S.gcnt += __popcll(gg);
     }
     if (sm) {
         int shift = 0, rank = 0, posF = 0;
@@ -211,40 +335,84 @@ __device__ __forceinline__ void s_push(SQueue &S, uint64_t ck, uint64_t pm) {
         S.fcnt = keep;
         wave_sync();
     }
+    b_make_room(S, thr);
 }
 
-// End-of-hop capacity rule. Returns true if live keys were dropped.
-__device__ bool s_capacity(SQueue &S, float thr, int L) {
+// Keeps the keys <= T of an array of this wave (LDS or workspace); returns the count.
+__device__ __forceinline__ int keep_upto(uint64_t *A, int n, uint64_t T) {
     const int lane = lane_id();
-    if (S.fcnt + S.bcnt <= L) return false;
-    const uint32_t othr = ord_of(thr);
-    const int fl = __popcll(ballot(lane < S.fcnt && (uint32_t)(S.f >> 32) <= othr));
-    S.f = lane < fl ? S.f : KEY_MAX;
-    S.fcnt = fl;
-    S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
-    if (S.fcnt + S.bcnt <= L) return false;
-    if (L <= S.fcnt) {
-        S.f = lane < L ? S.f : KEY_MAX;
-        S.fcnt = L;
-        S.bcnt = 0;
-        S.beta = KEY_MAX;
-        return true;
-    }
-    const int keep = L - S.fcnt;
-    const uint64_t T = b_kth(S.B, S.bcnt, keep, S.stage, S.hist);
     int out = 0;
-    for (int base = 0; base < S.bcnt; base += WAVE) {
+    for (int base = 0; base < n; base += WAVE) {
         const int i = base + lane;
-        const uint64_t v = i < S.bcnt ? S.B[i] : KEY_MAX;
-        const bool k2 = i < S.bcnt && v <= T;
+        const uint64_t v = i < n ? A[i] : KEY_MAX;
+        const bool k2 = i < n && v <= T;
         const uint64_t m = ballot(k2);
         wave_sync();
-        if (k2) S.B[out + prefix_in(m)] = v;
+        if (k2) A[out + prefix_in(m)] = v;
         out += __popcll(m);
         wave_sync();
     }
-    S.bcnt = out;
-    return true;
+    return out;
+}
+
+// State after a cut of S (returned by value, see GrowOut).
+struct CutOut {
+    uint64_t f;
+    int fcnt, bcnt, gcnt;
+    bool b_cleared;  // B emptied by the cut (beta returns to KEY_MAX)
+    bool dropped;    // live keys were dropped
+};
+
+// More than L keys are held: drops the dead ones, then keeps the L smallest
+// live keys (F < B < G). Out of line: most hops never get here.
+__device__ __forceinline__ CutOut s_cut(uint64_t f, int fcnt, uint64_t *B, int bcnt, uint64_t *G,
+                                     int gcnt, uint64_t *stage, uint32_t *hist, float thr, int L) {
+    const int lane = lane_id();
+    CutOut o;
+    o.b_cleared = false;
+    o.dropped = false;
+    const uint32_t othr = ord_of(thr);
+    const int fl = __popcll(ballot(lane < fcnt && (uint32_t)(f >> 32) <= othr));
+    f = lane < fl ? f : KEY_MAX;
+    fcnt = fl;
+    bcnt = b_drop_dead(B, bcnt, thr);
+    gcnt = g_drop_dead(G, gcnt, thr);
+    if (fcnt + bcnt + gcnt > L) {
+        o.dropped = true;
+        if (fcnt + bcnt < L) {
+            const uint64_t T = b_kth(G, gcnt, L - fcnt - bcnt, stage, hist);
+            gcnt = keep_upto(G, gcnt, T);
+        } else {
+            gcnt = 0;
+            if (L <= fcnt) {
+                f = lane < L ? f : KEY_MAX;
+                fcnt = L;
+                bcnt = 0;
+                o.b_cleared = true;
+            } else if (fcnt + bcnt > L) {
+                const uint64_t T = b_kth(B, bcnt, L - fcnt, stage, hist);
+                bcnt = keep_upto(B, bcnt, T);
+            }
+        }
+    }
+    o.f = f;
+    o.fcnt = fcnt;
+    o.bcnt = bcnt;
+    o.gcnt = gcnt;
+    return o;
+}
+
+// End-of-hop capacity rule. Returns true if live keys were dropped.
+__device__ __forceinline__ bool s_capacity(SQueue &S, float thr, int L) {
+    if (S.fcnt + S.bcnt + S.gcnt <= L) return false;
+    const CutOut o = s_cut(S.f, S.fcnt, S.B, S.bcnt, S.G, S.gcnt, S.stage, S.hist, thr, L);
+    S.f = o.f;
+    S.fcnt = o.fcnt;
+    S.bcnt = o.bcnt;
+    S.gcnt = o.gcnt;
+    if (S.gcnt == 0) S.phi = KEY_MAX;
+    if (o.b_cleared) S.beta = KEY_MAX;
+    return o.dropped;
 }
 
 // ---------------------------------------------------------------- R (results)
@@ -319,8 +487,12 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
 }
 
 // ---------------------------------------------------------------- the kernel
+// The stop variant's checkpoint needs more registers than a hop: with one or two
+// result registers it is held to 168 VGPRs (three waves per SIMD), with more to
+// 256 (two), and wide rows (QCH 12) are left to the compiler.
 template <int DT, int METRIC, int QCH, int RREG, bool FEAT>
-__global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FEAT ? (QCH >= 12 ? 1 : (RREG >= 4 ? 2 : 3)) : 1)))
+search_kernel(SearchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
     const int p = lane & 31;
@@ -453,6 +625,10 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         S.beta = KEY_MAX;
         S.B = Sq;
         S.bcnt = 0;
+        S.bcap = P.bcap;
+        S.phi = KEY_MAX;
+        S.G = P.gspace + (int64_t)blockIdx.x * P.gcap;
+        S.gcnt = 0;
         S.stage = stg;
         S.hist = hist;
         int hops = 0, evals = 0;
@@ -472,11 +648,39 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
         const int32_t *pv_tab = nullptr;
         int4 pa = make_int4(-1, -1, -1, -1), pb = pa;
 
+        // ---- excluded ids: marked in the visited set (checked ids never enter R)
+        if (!bad_query && P.ex_off != nullptr) {
+            const int64_t e0 = P.ex_off[qi], e1 = P.ex_off[qi + 1];
+            const int nex = (int)(e1 - e0);
+            if (!V.spilled && nex + WAVE + deg > hlimit) {
+                visit_spill(V, P);
+                flags |= DEG_FLAG_HASH_SPILL;
+            }
+            while (V.spilled && V.count + nex + WAVE + deg > V.limit) visit_grow(V, P);
+            int added = 0;
+            for (int64_t b = e0; b < e1; b += WAVE) {
+                const int64_t i = b + lane;
+                const int32_t id = i < e1 ? P.ex_ids[i] : -1;
+                const bool ok = id >= 0 && (int64_t)id < P.n;
+                bool fresh = false;
+                if (ok) {
+                    fresh = V.spilled ? cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), excl_mark(id))
+                                      : cas_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), excl_mark(id));
+                }
+                added += __popcll(ballot(fresh));
+                if (ballot(i < e1 && !ok) != 0) flags |= DEG_FLAG_BAD_ID;
+            }
+            V.count += added;
+            __threadfence_block();
+            wave_sync();
+        }
+
         // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
         if (!bad_query) {
             bool sv = lane < ns && seed_l >= 0 && (int64_t)seed_l < P.n;
             if (ballot(lane < ns && !sv) != 0) flags |= DEG_FLAG_BAD_ID;
-            bool isnew = visit_insert(V, seed_l, sv);
+            bool sx;
+            bool isnew = visit_insert(V, seed_l, sv, sx);
             uint64_t nm = ballot(isnew);
             int cnt = __popcll(nm);
             V.count += cnt;
@@ -485,9 +689,10 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             uint64_t ck = isnew ? make_key(cd, seed_l) : KEY_MAX;
             if (cnt > 0) dseed = key_dist(wave_min_u64(ck));
             int na;
-            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && seed_l != vtx), mbuf, t10, na);
+            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && !sx && seed_l != vtx), mbuf, t10,
+                          na);
             r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
-            if (cnt > 0) s_push(S, ck, nm);
+            if (cnt > 0) s_push(S, ck, nm, thr_of(r, onep));
             if (s_capacity(S, thr_of(r, onep), P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
         }
 
@@ -524,11 +729,24 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 const float dk = kq > 0 ? key_dist(kkey) : 0.f;
                 // entries of S before the kq-th result (F holds the smallest keys of S;
                 // B is counted only when every key of F is before it)
+                // (only the first 64 count: B is read while fewer are found, G only
+                // when its keys can precede the k-th result and F and B hold < 64)
                 int closer = __popcll(ballot(lane < S.fcnt && S.f < kkey));
                 if (closer == S.fcnt && closer < WAVE && S.bcnt > 0) {
-                    int cb = 0;
-                    for (int i = lane; i < S.bcnt; i += WAVE) cb += S.B[i] < kkey ? 1 : 0;
-                    closer += wave_sum_i32(cb);
+                    if (kkey >= S.beta && S.fcnt + S.bcnt >= WAVE && kkey > S.phi) {
+                        closer = WAVE;  // every key of F and B precedes it
+                    } else {
+                        for (int base = 0; base < S.bcnt && closer < WAVE; base += WAVE) {
+                            const int i = base + lane;
+                            closer += __popcll(ballot(i < S.bcnt && S.B[i] < kkey));
+                        }
+                    }
+                }
+                if (closer < WAVE && S.gcnt > 0 && kkey > S.phi) {
+                    for (int base = 0; base < S.gcnt && closer < WAVE; base += WAVE) {
+                        const int i = base + lane;
+                        closer += __popcll(ballot(i < S.gcnt && S.G[i] < kkey));
+                    }
                 }
                 closer = closer < WAVE ? closer : WAVE;
                 const bool fin_r = !__builtin_isinf(r) && !__builtin_isinf(rprev) && rprev > 0.f;
@@ -583,7 +801,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 }
                 if (want_stop) {
                     const float fs = lane < NFEAT ? __fmul_rn(__fsub_rn(fv, f_mean), f_istd) : 0.0f;
-                    const float z = mlp_logit(M, fs, hbuf);
+                    const float z = mlp_logit(M, P.stop_w, fs, hbuf);
                     if (z >= (hops >= P.stop_long_hops ? P.stop_tau_long : P.stop_tau)) {
                         flags |= DEG_FLAG_LEARNED_STOP;
                         break;
@@ -608,17 +826,17 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             } else if (V.spilled && V.count + deg > V.limit) {
                 visit_grow(V, P);
             }
-            bool isnew;
+            bool isnew, xl = false;
             if (V.spilled && s == pv && V.gtab == pv_tab) {
                 // the first probe round was read ahead: no table round trip here
                 run_nb = *pf;
                 int32_t unused = 0;
                 isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
                                                    hash_slot(nb, V.hgshift), nb, nb >= 0, nullptr,
-                                                   unused, pa, pb);
+                                                   unused, xl, pa, pb);
             } else {
                 // the runner-up's row is requested inside the check, after its table reads
-                isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
+                isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb, xl);
             }
             // read ahead the table slots of run_v's neighbours (run_v is the next pop
             // in about nine hops of ten): issued after this hop's claims, so nothing
@@ -642,8 +860,9 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
                 spec();
                 continue;
             }
-            // the table reads go out right after the new rows' loads
-            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb, spec);
+            // the table reads go out once the new rows are in
+            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb);
+            spec();
             const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
 
             // the closest new candidate is the likely next pop: load its row now
@@ -653,8 +872,8 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
             const uint64_t old_first = read_lane_u64(R[0], 0);
             int na;
-            const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && nb != vtx),
-                                           mbuf, t10, na);
+            const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck,
+                                           ballot(isnew && !xl && nb != vtx), mbuf, t10, na);
             if (chg) last_chg = hops;
             if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
             const float r_old = r;
@@ -668,7 +887,7 @@ __global__ void __launch_bounds__(64) search_kernel(SearchParams P) {
             const int np = __popcll(pm);
             n_acc_s = np;
             n_acc_r = na;
-            if (np > 0) s_push(S, ck, pm);
+            if (np > 0) s_push(S, ck, pm, thr);
             if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
         }
 

@@ -67,7 +67,9 @@ struct SearchParams {
     int32_t rerank;
     // state sizes
     int32_t L;      // capacity of S
-    int32_t scap;   // LDS slots of the S array beyond the 64 staging ones (>= L and >= pool)
+    int32_t bcap;   // LDS part of S beyond the 64 keys in registers (>= 256)
+    int32_t scap;   // LDS slots of the S array (>= bcap and >= the pool, for the rerank)
+    int64_t gcap;   // workspace part of S per wave (keys)
     int64_t nqrows; // rows of `queries` (batch mode bound check)
     int32_t H;      // LDS hash slots (power of 2)
     int32_t hshift; // 32 - log2(H)
@@ -88,6 +90,10 @@ struct SearchParams {
     int32_t *spill;      // the per-wave regions
     int32_t *pool;       // npool tables of hg_cap slots
     int32_t *pool_owner; // npool words: 0 free, 1 taken
+    uint64_t *gspace;    // per wave gcap keys: the far part of S
+    // per-query exclusion lists (CSR over queries; nullable)
+    const int64_t *ex_off;
+    const int32_t *ex_ids;
     // learned stop
     const uint16_t *stop_w;
     const float *stop_mean;
@@ -286,7 +292,7 @@ __device__ __forceinline__ float half_reduce(float a) {
 template <int DL, int QCH>
 constexpr int dist_rounds_max() {
     constexpr int WPC = DL == DT_F32 ? 4 : (DL == DT_BF16 ? 2 : 1);  // 32-bit words per chunk
-    constexpr int BUDGET = QCH >= 12 ? 96 : 32;
+    constexpr int BUDGET = QCH >= 12 ? 96 : 16;
     constexpr int G0 = BUDGET / (QCH * WPC);
     constexpr int GMAX = QCH >= 12 ? 4 : 8;
     return G0 < 1 ? 1 : (G0 > GMAX ? GMAX : G0);
@@ -485,25 +491,36 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t id, int shift) {
     return ((uint32_t)id * 0x9E3779B1u) >> shift;
 }
 
+// Slot values of the visited tables: -1 empty, id >= 0 checked, and
+// mark(id) = -(id + 2) <= -2 for an excluded id not checked yet (it is claimed
+// like an empty slot, and the claim reports the exclusion).
+__device__ __forceinline__ int32_t excl_mark(int32_t id) { return -id - 2; }
+__device__ __forceinline__ int32_t slot_id(int32_t v) { return v >= 0 ? v : -v - 2; }
+
 // Position, within an aligned group of four slots, of the first slot at or
-// after position j0 that holds `id` or is empty: 0..3 for an empty slot, 4..7
-// for the slot holding id, -1 if neither occurs. Plain selects, no branches.
-__device__ __forceinline__ int group_scan(const int4 &q, uint32_t j0, int32_t id) {
+// after position j0 that holds `id`, its mark `mk`, or is empty: 0..3 for an
+// empty or marked slot, 4..7 for the slot holding id, -1 if none occurs.
+// Plain selects, no branches.
+__device__ __forceinline__ int group_scan(const int4 &q, uint32_t j0, int32_t id, int32_t mk) {
     int c = -1;
-    c = (q.w == id || q.w == -1) ? (q.w == id ? 7 : 3) : c;
-    c = (j0 <= 2u && (q.z == id || q.z == -1)) ? (q.z == id ? 6 : 2) : c;
-    c = (j0 <= 1u && (q.y == id || q.y == -1)) ? (q.y == id ? 5 : 1) : c;
-    c = (j0 == 0u && (q.x == id || q.x == -1)) ? (q.x == id ? 4 : 0) : c;
+    c = (q.w == id || q.w == -1 || q.w == mk) ? (q.w == id ? 7 : 3) : c;
+    c = (j0 <= 2u && (q.z == id || q.z == -1 || q.z == mk)) ? (q.z == id ? 6 : 2) : c;
+    c = (j0 <= 1u && (q.y == id || q.y == -1 || q.y == mk)) ? (q.y == id ? 5 : 1) : c;
+    c = (j0 == 0u && (q.x == id || q.x == -1 || q.x == mk)) ? (q.x == id ? 4 : 0) : c;
     return c;
+}
+__device__ __forceinline__ int32_t int4_at(const int4 &q, int j) {
+    return j == 0 ? q.x : (j == 1 ? q.y : (j == 2 ? q.z : q.w));
 }
 
 // The same over eight slots read as two groups of four (the aligned group
 // holding position j0, then the next group, whose positions all count):
 // 0..7 for the first empty slot, 8..15 for the slot holding id (offsets from
 // the first group's start), -1 if neither occurs.
-__device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_t j0, int32_t id) {
-    const int c0 = group_scan(a, j0, id);
-    const int c1 = group_scan(b, 0u, id);
+__device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_t j0, int32_t id,
+                                           int32_t mk) {
+    const int c0 = group_scan(a, j0, id, mk);
+    const int c1 = group_scan(b, 0u, id, mk);
     const int r1 = c1 < 0 ? -1 : (c1 >= 4 ? c1 + 8 : c1 + 4);  // 4..7 empty, 12..15 present
     const int r0 = c0 >= 4 ? c0 + 4 : c0;                        // 0..3 empty, 8..11 present
     return c0 >= 0 ? r0 : r1;
@@ -518,33 +535,41 @@ __device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_
 // the same as with one-slot probing. A stale read can only show -1 where an id
 // already is: the CAS then returns that id (done) or another one (the probe
 // goes on after that slot).
-// Returns true where id was not in the set.
-__device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
+// Returns true where id was not in the set; `excl` then tells whether it was
+// marked excluded.
+__device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
+                                             bool &excl) {
+    const int32_t mk = excl_mark(id);
     for (;;) {
         const uint32_t g = s & ~3u;
         const int4 a = *reinterpret_cast<const int4 *>(tab + g);
         const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
-        const int c = group_scan8(a, b, s & 3u, id);
+        const int c = group_scan8(a, b, s & 3u, id, mk);
         if (c >= 8) return false;
         if (c < 0) {
             s = (g + 8u) & msk;
             continue;
         }
         const uint32_t t = (g + (uint32_t)c) & msk;
-        const int32_t old = atomicCAS(&tab[t], -1, id);
-        if (old == -1) return true;
+        const int32_t seen = c < 4 ? int4_at(a, c) : int4_at(b, c - 4);
+        const int32_t old = atomicCAS(&tab[t], seen, id);
+        if (old == seen) {
+            excl = seen == mk;
+            return true;
+        }
         if (old == id) return false;
         s = (t + 1u) & msk;
     }
 }
 
-// Linear-probing insert by compare-and-swap on each probed slot (one round
-// trip per probe; suited to a sparsely filled table in global memory).
-__device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
+// Linear-probing insert of the slot value v (an id or a mark) by
+// compare-and-swap on each probed slot, from slot s (one round trip per probe;
+// for moving a table and for the marks placed at the start of a query).
+__device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t v) {
     for (;;) {
-        const int32_t old = atomicCAS(&tab[s], -1, id);
+        const int32_t old = atomicCAS(&tab[s], -1, v);
         if (old == -1) return true;
-        if (old == id) return false;
+        if (old == v || slot_id(old) == slot_id(v)) return false;
         s = (s + 1u) & msk;
     }
 }
@@ -569,8 +594,10 @@ __device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t 
 template <bool PF, bool FIRST = false>
 __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
                                               bool act, const int32_t *pf, int32_t &pfv,
-                                              const int4 &a0 = int4{}, const int4 &b0 = int4{}) {
+                                              bool &excl, const int4 &a0 = int4{},
+                                              const int4 &b0 = int4{}) {
     const int lane = lane_id();
+    const int32_t mk = excl_mark(id);
     bool isnew = false, pending = act;
     if (ballot(pending) == 0) {
         if (PF) pfv = *pf;
@@ -594,11 +621,14 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
             pfv = *pf;
         }
         uint32_t target = 0xFFFFFFFFu;
+        bool tmark = false;
         if (pending) {
-            const int c = group_scan8(a, b, s & 3u, id);
+            const int c = group_scan8(a, b, s & 3u, id, mk);
             if (c >= 8) pending = false;
-            else if (c >= 0) target = (g + (uint32_t)c) & msk;
-            else s = (g + 8u) & msk;
+            else if (c >= 0) {
+                target = (g + (uint32_t)c) & msk;
+                tmark = (c < 4 ? int4_at(a, c) : int4_at(b, c - 4)) == mk;
+            } else s = (g + 8u) & msk;
         }
         // claims: lowest lane per slot wins; a loser holding the winner's id
         // (the same id twice in one adjacency row) finds it present
@@ -618,6 +648,7 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
         } else if (win) {
             tab[target] = id;
             isnew = true;
+            excl = tmark;
             pending = false;
         } else if (target != 0xFFFFFFFFu) {
             s = (target + 1u) & msk;  // the slot is taken by a lower lane: probe on
@@ -639,22 +670,24 @@ __device__ __forceinline__ void spec_read(const Visited &V, int32_t id, bool act
 }
 
 // Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the
-// set. With PF also loads pfv = *pf (pf valid in every lane), issued after the
-// workspace-table reads.
+// set, and then `excl` tells whether it was marked excluded. With PF also loads
+// pfv = *pf (pf valid in every lane), issued after the workspace-table reads.
 template <bool PF>
 __device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act, const int32_t *pf,
-                                             int32_t &pfv) {
+                                             int32_t &pfv, bool &excl) {
+    excl = false;
     if (!V.spilled) {
         if (PF) pfv = *pf;
         bool isnew = false;
-        if (act) isnew = probe_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), id);
+        if (act) isnew = probe_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), id, excl);
         return isnew;
     }
-    return global_insert<PF>(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id, act, pf, pfv);
+    return global_insert<PF>(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id, act, pf,
+                             pfv, excl);
 }
-__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
+__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act, bool &excl) {
     int32_t unused = 0;
-    return visit_insert<false>(V, id, act, nullptr, unused);
+    return visit_insert<false>(V, id, act, nullptr, unused, excl);
 }
 
 __device__ __forceinline__ int ilog2_dev(int x) { return 31 - __builtin_clz((unsigned)x); }
@@ -682,8 +715,8 @@ __device__ __forceinline__ void visit_spill(Visited &V, const SearchParams &P) {
     table_use(V, V.region, P.hg0, P.hg_cap);
     V.spilled = true;
     for (int i = lane_id(); i < V.H; i += WAVE) {
-        const int32_t id = V.htab[i];
-        if (id >= 0) cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id);
+        const int32_t v = V.htab[i];
+        if (v != -1) cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(slot_id(v), V.hgshift), v);
     }
     __threadfence();
     wave_sync();
@@ -691,13 +724,13 @@ __device__ __forceinline__ void visit_spill(Visited &V, const SearchParams &P) {
 
 // Takes a free shared table (waiting while all are held: holders never wait,
 // their searches end, and they give the table back at the end of their query).
-__device__ int pool_take(const SearchParams &P) {
+__device__ __forceinline__ int pool_take(int npool, int *owner) {
     int slot = -1;
     for (;;) {
         if (lane_id() == 0) {
-            for (int t = 0; t < P.npool; ++t) {
-                const int i = (int)((blockIdx.x + (unsigned)t) % (unsigned)P.npool);
-                if (atomicCAS(&P.pool_owner[i], 0, 1) == 0) {
+            for (int t = 0; t < npool; ++t) {
+                const int i = (int)((blockIdx.x + (unsigned)t) % (unsigned)npool);
+                if (atomicCAS(&owner[i], 0, 1) == 0) {
                     slot = i;
                     break;
                 }
@@ -719,35 +752,55 @@ __device__ __forceinline__ void pool_give(Visited &V, const SearchParams &P) {
     V.pslot = -1;
 }
 
-// Moves the workspace table to one four times larger (or the shared table).
-__device__ void visit_grow(Visited &V, const SearchParams &P) {
-    int ns = V.Hg * 4;
-    if (ns > P.hg_cap) ns = P.hg_cap;
-    int32_t *nt;
-    int64_t noff = V.roff;
-    if (ns <= P.hg_priv) {
-        noff = V.roff + V.Hg;
-        nt = V.region + noff;
+// Where a table moved to (returned by value: the caller's state never has its
+// address taken, so it stays in registers).
+struct GrowOut {
+    int32_t *t;
+    int64_t off;
+    int slots;
+    int pslot;
+};
+
+// Moves workspace table `old` (on slots, at offset roff of the region) to one
+// four times larger, or to a shared table once that passes hg_priv slots.
+// Kept out of line: it runs a few times per query at most.
+__device__ __forceinline__ GrowOut grow_table(const int32_t *old, int on, int32_t *region, int64_t roff,
+                                           int hg_priv, int hg_cap, int32_t *pool, int npool,
+                                           int *owner) {
+    GrowOut o;
+    int ns = on * 4;
+    if (ns > hg_cap) ns = hg_cap;
+    o.off = roff;
+    o.pslot = -1;
+    if (ns <= hg_priv) {
+        o.off = roff + on;
+        o.t = region + o.off;
     } else {
-        ns = P.hg_cap;
-        V.pslot = pool_take(P);
-        nt = P.pool + (int64_t)V.pslot * P.hg_cap;
+        ns = hg_cap;
+        o.pslot = pool_take(npool, owner);
+        o.t = pool + (int64_t)o.pslot * hg_cap;
     }
-    table_clear(nt, ns);
+    o.slots = ns;
+    table_clear(o.t, ns);
     __threadfence();
     wave_sync();
-    const int32_t *old = V.gtab;
-    const int on = V.Hg;
     const uint32_t msk = (uint32_t)ns - 1u;
     const int sh = 32 - ilog2_dev(ns);
     for (int i = lane_id(); i < on; i += WAVE) {
-        const int32_t id = old[i];
-        if (id >= 0) cas_insert(nt, msk, hash_slot(id, sh), id);
+        const int32_t v = old[i];
+        if (v != -1) cas_insert(o.t, msk, hash_slot(slot_id(v), sh), v);
     }
     __threadfence();
     wave_sync();
-    V.roff = noff;
-    table_use(V, nt, ns, P.hg_cap);
+    return o;
+}
+
+__device__ __forceinline__ void visit_grow(Visited &V, const SearchParams &P) {
+    const GrowOut o = grow_table(V.gtab, V.Hg, V.region, V.roff, P.hg_priv, P.hg_cap, P.pool,
+                                 P.npool, P.pool_owner);
+    if (o.pslot >= 0) V.pslot = o.pslot;
+    V.roff = o.off;
+    table_use(V, o.t, o.slots, P.hg_cap);
 }
 
 }  // namespace degk

@@ -330,3 +330,38 @@ def test_parity_cfg2_full_size_sampled(A):
         assert (st[:, 2] & A.FLAG_HASH_FULL == 0).all()
         # BF16 traversal is lossless on integer data below 256: same result
         assert (ids16.cpu().numpy() == ids).all() and (ds16.cpu().numpy() == ds).all()
+
+
+@pytest.mark.parametrize("mode", ["vector", "indexed"])
+def test_parity_exclusion_lists(A, mode):
+    # random per-query exclusion lists (Sec. 4): excluded ids are checked and
+    # expanded but never returned; some lists are long enough to move the visited
+    # set to the workspace before the search starts, some hold the seed
+    x, adj = graph(1500, 24, 30)
+    nq = 120
+    r = synth.rng(80 if mode == "vector" else 81)
+    lists = []
+    for i in range(nq):
+        n_ex = int(r.choice([0, 3, 40, 600]))
+        ex = r.choice(1500, size=n_ex, replace=False).tolist()
+        if i % 7 == 0:
+            ex = ex + [0] + ex[:2]  # the seed, and repeated ids
+        lists.append(ex)
+    store = A.VectorStore(dev(x), "f32")
+    g = A.DeviceGraph(dev(adj))
+    excl = A.exclusion_lists(lists)
+    say("exclusion lists", mode)
+    if mode == "vector":
+        q = queries_for("int", 82, nq, 24)
+        ids, ds, st = A.search(store, g, dev(q), dev(np.zeros((nq, 1), np.int32)), 20, 0.1,
+                               queue_cap=BIG_L, exclude=excl)
+        ref = oracle.range_search(x, adj, q, [0], 20, 0.1, cap_L=BIG_L, exclude=lists)
+    else:
+        qids = r.choice(1500, size=nq, replace=False).astype(np.int32)
+        ids, ds, st = A.search_indexed(store, g, dev(qids), 20, 0.1, queue_cap=BIG_L, exclude=excl)
+        ref = oracle.range_search_indexed(x, adj, qids, 20, 0.1, cap_L=BIG_L, exclude=lists)
+    torch.cuda.synchronize()
+    got = (ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy())
+    assert_parity(got, ref, "exclusion lists %s" % mode)
+    for i in range(nq):
+        assert not set(got[0][i].tolist()) & set(lists[i])

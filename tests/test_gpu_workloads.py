@@ -83,11 +83,11 @@ def test_exploration_ip_full_size_sampled(A):
     store = A.VectorStore(dev(base), "f32", metric)
     G = A.DeviceGraph(dev(adj))
     k = 100
-    L = max(256, 8 * k)  # the library's default capacity of S
+    L = 16384  # the library's default capacity of S, passed explicitly
     sample = synth.rng(80).choice(len(qids), size=120, replace=False)
     rec = {}
     for eps in (0.0, 0.1):
-        ids, ds, st = A.search_indexed(store, G, dev(qids), k, eps)
+        ids, ds, st = A.search_indexed(store, G, dev(qids), k, eps, queue_cap=L)
         torch.cuda.synchronize()
         ids, ds, st = ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()
         assert not (ids == qids[:, None]).any()  # the query vertex is never returned
@@ -108,14 +108,14 @@ def test_precision_stress_full_size(A):
     G = A.DeviceGraph(dev(adj))
     xb = dev(base)
     k, eps = 100, 0.1
-    L = max(256, 8 * k)
+    L = 16384  # the library's default capacity of S, passed explicitly
     seeds = dev(np.full((q.shape[0], 1), seed, np.int32))
     sample = synth.rng(81).choice(q.shape[0], size=60, replace=False)
     nthr = oracle.nthreads_default()
     table = {}
     for dtype in ("f32", "bf16", "fp8"):
         store = A.VectorStore(xb, dtype, metric)
-        ids, ds, st = A.search(store, G, dev(q), seeds, k, eps)
+        ids, ds, st = A.search(store, G, dev(q), seeds, k, eps, queue_cap=L)
         torch.cuda.synchronize()
         ids, ds, st = ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()
         if dtype == "f32":
@@ -157,11 +157,11 @@ def test_batch_stream_full_size_sampled(A):
     sv = np.where(kind == 1, desc["vertex"], seed).astype(np.int32)
     kk, ee = desc["k"], desc["eps"]
     descs, total, kmax = A.make_descs(kind, sv, np.arange(nq, dtype=np.int64), kk, ee)
-    L = max(256, 8 * kmax)  # the library's default capacity of S for this launch
+    L = 16384  # the library's default capacity of S, passed explicitly
     say("cfg5 batch", nq, total, kmax)
     store = A.VectorStore(dev(base), "f32", metric)
     G = A.DeviceGraph(dev(adj))
-    ids, ds, st = A.search_batch(store, G, dev(q), descs, nq, total, kmax)
+    ids, ds, st = A.search_batch(store, G, dev(q), descs, nq, total, kmax, queue_cap=L)
     torch.cuda.synchronize()
     ids, ds, st = ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()
     off = np.concatenate([[0], np.cumsum(kk)[:-1]])
