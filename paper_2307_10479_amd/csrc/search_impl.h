@@ -189,7 +189,7 @@ __device__ __forceinline__ void f_from_stage(SQueue &S, int c) {
 
 // B is empty: it takes back the smallest live keys of G (up to half its capacity;
 // usually most keys of G are dead by then and all live ones fit).
-__device__ void b_from_g(SQueue &S, float thr) {
+__device__ __forceinline__ void b_from_g(SQueue &S, float thr) {
     S.gcnt = g_drop_dead(S.G, S.gcnt, thr);
     if (S.gcnt == 0) {
         S.phi = KEY_MAX;
@@ -242,7 +242,7 @@ __device__ void b_from_g(SQueue &S, float thr) {
 
 // F is empty: move the (up to) 64 smallest live keys of B (refilled from G when
 // it is empty) into F.
-__device__ void s_refill(SQueue &S, float thr) {
+__device__ __forceinline__ void s_refill(SQueue &S, float thr) {
     const int lane = lane_id();
     S.bcnt = b_drop_dead(S.B, S.bcnt, thr);
     if (S.bcnt == 0 && S.gcnt > 0) b_from_g(S, thr);
@@ -648,39 +648,29 @@ search_kernel(SearchParams P) {
         const int32_t *pv_tab = nullptr;
         int4 pa = make_int4(-1, -1, -1, -1), pb = pa;
 
-        // ---- excluded ids: marked in the visited set (checked ids never enter R)
+        // ---- exclusion list of this query: its ids are checked, enter S and are
+        // expanded like any other, but never enter R (tested where a candidate
+        // could enter R)
+        const int32_t *exl = nullptr;
+        int nex = 0;
         if (!bad_query && P.ex_off != nullptr) {
             const int64_t e0 = P.ex_off[qi], e1 = P.ex_off[qi + 1];
-            const int nex = (int)(e1 - e0);
-            if (!V.spilled && nex + WAVE + deg > hlimit) {
-                visit_spill(V, P);
-                flags |= DEG_FLAG_HASH_SPILL;
+            exl = P.ex_ids + e0;
+            nex = e1 > e0 ? (int)(e1 - e0) : 0;
+            if (e1 < e0) flags |= DEG_FLAG_BAD_ID;
+            bool badx = false;
+            for (int i = lane; i < nex; i += WAVE) {
+                const int32_t id = exl[i];
+                badx |= id < 0 || (int64_t)id >= P.n;
             }
-            while (V.spilled && V.count + nex + WAVE + deg > V.limit) visit_grow(V, P);
-            int added = 0;
-            for (int64_t b = e0; b < e1; b += WAVE) {
-                const int64_t i = b + lane;
-                const int32_t id = i < e1 ? P.ex_ids[i] : -1;
-                const bool ok = id >= 0 && (int64_t)id < P.n;
-                bool fresh = false;
-                if (ok) {
-                    fresh = V.spilled ? cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), excl_mark(id))
-                                      : cas_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), excl_mark(id));
-                }
-                added += __popcll(ballot(fresh));
-                if (ballot(i < e1 && !ok) != 0) flags |= DEG_FLAG_BAD_ID;
-            }
-            V.count += added;
-            __threadfence_block();
-            wave_sync();
+            if (ballot(badx) != 0) flags |= DEG_FLAG_BAD_ID;
         }
 
         // ---- seeds: C <- seeds, each evaluated once, all enter S, non-excluded enter R
         if (!bad_query) {
             bool sv = lane < ns && seed_l >= 0 && (int64_t)seed_l < P.n;
             if (ballot(lane < ns && !sv) != 0) flags |= DEG_FLAG_BAD_ID;
-            bool sx;
-            bool isnew = visit_insert(V, seed_l, sv, sx);
+            bool isnew = visit_insert(V, seed_l, sv);
             uint64_t nm = ballot(isnew);
             int cnt = __popcll(nm);
             V.count += cnt;
@@ -689,8 +679,9 @@ search_kernel(SearchParams P) {
             uint64_t ck = isnew ? make_key(cd, seed_l) : KEY_MAX;
             if (cnt > 0) dseed = key_dist(wave_min_u64(ck));
             int na;
-            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, ballot(isnew && !sx && seed_l != vtx), mbuf, t10,
-                          na);
+            uint64_t rm = ballot(isnew && seed_l != vtx);
+            if (nex > 0) rm &= ~excluded_lanes(exl, nex, seed_l, rm);
+            r_merge<RREG>(R, rcnt, total, ovf, kp, ck, rm, mbuf, t10, na);
             r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
             if (cnt > 0) s_push(S, ck, nm, thr_of(r, onep));
             if (s_capacity(S, thr_of(r, onep), P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
@@ -826,17 +817,17 @@ search_kernel(SearchParams P) {
             } else if (V.spilled && V.count + deg > V.limit) {
                 visit_grow(V, P);
             }
-            bool isnew, xl = false;
+            bool isnew;
             if (V.spilled && s == pv && V.gtab == pv_tab) {
                 // the first probe round was read ahead: no table round trip here
                 run_nb = *pf;
                 int32_t unused = 0;
                 isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
                                                    hash_slot(nb, V.hgshift), nb, nb >= 0, nullptr,
-                                                   unused, xl, pa, pb);
+                                                   unused, pa, pb);
             } else {
                 // the runner-up's row is requested inside the check, after its table reads
-                isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb, xl);
+                isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
             }
             // read ahead the table slots of run_v's neighbours (run_v is the next pop
             // in about nine hops of ten): issued after this hop's claims, so nothing
@@ -872,8 +863,9 @@ search_kernel(SearchParams P) {
             // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
             const uint64_t old_first = read_lane_u64(R[0], 0);
             int na;
-            const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck,
-                                           ballot(isnew && !xl && nb != vtx), mbuf, t10, na);
+            uint64_t rm = ballot(isnew && nb != vtx);
+            if (nex > 0) rm &= ~excluded_lanes(exl, nex, nb, rm & ballot(cd <= r));
+            const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, rm, mbuf, t10, na);
             if (chg) last_chg = hops;
             if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
             const float r_old = r;

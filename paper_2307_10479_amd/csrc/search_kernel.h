@@ -491,36 +491,25 @@ __device__ __forceinline__ uint32_t hash_slot(int32_t id, int shift) {
     return ((uint32_t)id * 0x9E3779B1u) >> shift;
 }
 
-// Slot values of the visited tables: -1 empty, id >= 0 checked, and
-// mark(id) = -(id + 2) <= -2 for an excluded id not checked yet (it is claimed
-// like an empty slot, and the claim reports the exclusion).
-__device__ __forceinline__ int32_t excl_mark(int32_t id) { return -id - 2; }
-__device__ __forceinline__ int32_t slot_id(int32_t v) { return v >= 0 ? v : -v - 2; }
-
 // Position, within an aligned group of four slots, of the first slot at or
-// after position j0 that holds `id`, its mark `mk`, or is empty: 0..3 for an
-// empty or marked slot, 4..7 for the slot holding id, -1 if none occurs.
-// Plain selects, no branches.
-__device__ __forceinline__ int group_scan(const int4 &q, uint32_t j0, int32_t id, int32_t mk) {
+// after position j0 that holds `id` or is empty: 0..3 for an empty slot, 4..7
+// for the slot holding id, -1 if neither occurs. Plain selects, no branches.
+__device__ __forceinline__ int group_scan(const int4 &q, uint32_t j0, int32_t id) {
     int c = -1;
-    c = (q.w == id || q.w == -1 || q.w == mk) ? (q.w == id ? 7 : 3) : c;
-    c = (j0 <= 2u && (q.z == id || q.z == -1 || q.z == mk)) ? (q.z == id ? 6 : 2) : c;
-    c = (j0 <= 1u && (q.y == id || q.y == -1 || q.y == mk)) ? (q.y == id ? 5 : 1) : c;
-    c = (j0 == 0u && (q.x == id || q.x == -1 || q.x == mk)) ? (q.x == id ? 4 : 0) : c;
+    c = (q.w == id || q.w == -1) ? (q.w == id ? 7 : 3) : c;
+    c = (j0 <= 2u && (q.z == id || q.z == -1)) ? (q.z == id ? 6 : 2) : c;
+    c = (j0 <= 1u && (q.y == id || q.y == -1)) ? (q.y == id ? 5 : 1) : c;
+    c = (j0 == 0u && (q.x == id || q.x == -1)) ? (q.x == id ? 4 : 0) : c;
     return c;
-}
-__device__ __forceinline__ int32_t int4_at(const int4 &q, int j) {
-    return j == 0 ? q.x : (j == 1 ? q.y : (j == 2 ? q.z : q.w));
 }
 
 // The same over eight slots read as two groups of four (the aligned group
 // holding position j0, then the next group, whose positions all count):
 // 0..7 for the first empty slot, 8..15 for the slot holding id (offsets from
 // the first group's start), -1 if neither occurs.
-__device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_t j0, int32_t id,
-                                           int32_t mk) {
-    const int c0 = group_scan(a, j0, id, mk);
-    const int c1 = group_scan(b, 0u, id, mk);
+__device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_t j0, int32_t id) {
+    const int c0 = group_scan(a, j0, id);
+    const int c1 = group_scan(b, 0u, id);
     const int r1 = c1 < 0 ? -1 : (c1 >= 4 ? c1 + 8 : c1 + 4);  // 4..7 empty, 12..15 present
     const int r0 = c0 >= 4 ? c0 + 4 : c0;                        // 0..3 empty, 8..11 present
     return c0 >= 0 ? r0 : r1;
@@ -535,41 +524,33 @@ __device__ __forceinline__ int group_scan8(const int4 &a, const int4 &b, uint32_
 // the same as with one-slot probing. A stale read can only show -1 where an id
 // already is: the CAS then returns that id (done) or another one (the probe
 // goes on after that slot).
-// Returns true where id was not in the set; `excl` then tells whether it was
-// marked excluded.
-__device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
-                                             bool &excl) {
-    const int32_t mk = excl_mark(id);
+// Returns true where id was not in the set.
+__device__ __forceinline__ bool probe_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id) {
     for (;;) {
         const uint32_t g = s & ~3u;
         const int4 a = *reinterpret_cast<const int4 *>(tab + g);
         const int4 b = *reinterpret_cast<const int4 *>(tab + ((g + 4u) & msk));
-        const int c = group_scan8(a, b, s & 3u, id, mk);
+        const int c = group_scan8(a, b, s & 3u, id);
         if (c >= 8) return false;
         if (c < 0) {
             s = (g + 8u) & msk;
             continue;
         }
         const uint32_t t = (g + (uint32_t)c) & msk;
-        const int32_t seen = c < 4 ? int4_at(a, c) : int4_at(b, c - 4);
-        const int32_t old = atomicCAS(&tab[t], seen, id);
-        if (old == seen) {
-            excl = seen == mk;
-            return true;
-        }
+        const int32_t old = atomicCAS(&tab[t], -1, id);
+        if (old == -1) return true;
         if (old == id) return false;
         s = (t + 1u) & msk;
     }
 }
 
-// Linear-probing insert of the slot value v (an id or a mark) by
-// compare-and-swap on each probed slot, from slot s (one round trip per probe;
-// for moving a table and for the marks placed at the start of a query).
+// Linear-probing insert of id v by compare-and-swap on each probed slot, from
+// slot s (one round trip per probe; for moving a table).
 __device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t v) {
     for (;;) {
         const int32_t old = atomicCAS(&tab[s], -1, v);
         if (old == -1) return true;
-        if (old == v || slot_id(old) == slot_id(v)) return false;
+        if (old == v) return false;
         s = (s + 1u) & msk;
     }
 }
@@ -594,10 +575,9 @@ __device__ __forceinline__ bool cas_insert(int32_t *tab, uint32_t msk, uint32_t 
 template <bool PF, bool FIRST = false>
 __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32_t s, int32_t id,
                                               bool act, const int32_t *pf, int32_t &pfv,
-                                              bool &excl, const int4 &a0 = int4{},
+                                              const int4 &a0 = int4{},
                                               const int4 &b0 = int4{}) {
     const int lane = lane_id();
-    const int32_t mk = excl_mark(id);
     bool isnew = false, pending = act;
     if (ballot(pending) == 0) {
         if (PF) pfv = *pf;
@@ -621,14 +601,11 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
             pfv = *pf;
         }
         uint32_t target = 0xFFFFFFFFu;
-        bool tmark = false;
         if (pending) {
-            const int c = group_scan8(a, b, s & 3u, id, mk);
+            const int c = group_scan8(a, b, s & 3u, id);
             if (c >= 8) pending = false;
-            else if (c >= 0) {
-                target = (g + (uint32_t)c) & msk;
-                tmark = (c < 4 ? int4_at(a, c) : int4_at(b, c - 4)) == mk;
-            } else s = (g + 8u) & msk;
+            else if (c >= 0) target = (g + (uint32_t)c) & msk;
+            else s = (g + 8u) & msk;
         }
         // claims: lowest lane per slot wins; a loser holding the winner's id
         // (the same id twice in one adjacency row) finds it present
@@ -648,7 +625,6 @@ __device__ __forceinline__ bool global_insert(int32_t *tab, uint32_t msk, uint32
         } else if (win) {
             tab[target] = id;
             isnew = true;
-            excl = tmark;
             pending = false;
         } else if (target != 0xFFFFFFFFu) {
             s = (target + 1u) & msk;  // the slot is taken by a lower lane: probe on
@@ -669,25 +645,44 @@ __device__ __forceinline__ void spec_read(const Visited &V, int32_t id, bool act
     b = *reinterpret_cast<const int4 *>(V.gtab + ((g + 4u) & msk));
 }
 
+// Lanes of `cand` whose id is on the query's exclusion list ex[0 .. nex): the
+// wave reads the list 64 ids at a time and compares each candidate with every
+// id read (a ballot per candidate). Only candidates that could enter the result
+// are checked, so a hop without one reads nothing.
+__device__ __forceinline__ uint64_t excluded_lanes(const int32_t *ex, int nex, int32_t id,
+                                                   uint64_t cand) {
+    const int lane = lane_id();
+    uint64_t hit = 0;
+    for (int b = 0; b < nex && cand != 0; b += WAVE) {
+        const int32_t e = b + lane < nex ? ex[b + lane] : -1;
+        for (uint64_t m = cand; m; m &= m - 1) {
+            const int c = (int)__builtin_ctzll(m);
+            const int32_t ic = __builtin_amdgcn_readlane(id, c);
+            if (ballot(e == ic) != 0) hit |= 1ull << c;
+        }
+        cand &= ~hit;
+    }
+    return hit;
+}
+
 // Inserts `id` (lane-wise, `act` lanes); returns true where id was not in the
-// set, and then `excl` tells whether it was marked excluded. With PF also loads
+// set. With PF also loads
 // pfv = *pf (pf valid in every lane), issued after the workspace-table reads.
 template <bool PF>
 __device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act, const int32_t *pf,
-                                             int32_t &pfv, bool &excl) {
-    excl = false;
+                                             int32_t &pfv) {
     if (!V.spilled) {
         if (PF) pfv = *pf;
         bool isnew = false;
-        if (act) isnew = probe_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), id, excl);
+        if (act) isnew = probe_insert(V.htab, (uint32_t)V.H - 1u, hash_slot(id, V.hshift), id);
         return isnew;
     }
     return global_insert<PF>(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(id, V.hgshift), id, act, pf,
-                             pfv, excl);
+                             pfv);
 }
-__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act, bool &excl) {
+__device__ __forceinline__ bool visit_insert(Visited &V, int32_t id, bool act) {
     int32_t unused = 0;
-    return visit_insert<false>(V, id, act, nullptr, unused, excl);
+    return visit_insert<false>(V, id, act, nullptr, unused);
 }
 
 __device__ __forceinline__ int ilog2_dev(int x) { return 31 - __builtin_clz((unsigned)x); }
@@ -716,7 +711,7 @@ __device__ __forceinline__ void visit_spill(Visited &V, const SearchParams &P) {
     V.spilled = true;
     for (int i = lane_id(); i < V.H; i += WAVE) {
         const int32_t v = V.htab[i];
-        if (v != -1) cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(slot_id(v), V.hgshift), v);
+        if (v != -1) cas_insert(V.gtab, (uint32_t)V.Hg - 1u, hash_slot(v, V.hgshift), v);
     }
     __threadfence();
     wave_sync();
@@ -788,7 +783,7 @@ __device__ __forceinline__ GrowOut grow_table(const int32_t *old, int on, int32_
     const int sh = 32 - ilog2_dev(ns);
     for (int i = lane_id(); i < on; i += WAVE) {
         const int32_t v = old[i];
-        if (v != -1) cas_insert(o.t, msk, hash_slot(slot_id(v), sh), v);
+        if (v != -1) cas_insert(o.t, msk, hash_slot(v, sh), v);
     }
     __threadfence();
     wave_sync();
