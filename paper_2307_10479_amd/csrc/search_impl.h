@@ -488,10 +488,11 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
 
 // ---------------------------------------------------------------- the kernel
 // The stop variant's checkpoint needs more registers than a hop: with one or two
-// result registers it is held to 168 VGPRs (three waves per SIMD), with more to
-// 256 (two), and wide rows (QCH 12) are left to the compiler.
+// result registers it is held to 128 VGPRs (four waves per SIMD; the few spills
+// fall outside the hop loop), with more to 256 (two), and wide rows (QCH 12)
+// are left to the compiler.
 template <int DT, int METRIC, int QCH, int RREG, bool FEAT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FEAT ? (QCH >= 12 ? 1 : (RREG >= 4 ? 2 : 3)) : 1)))
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FEAT ? (QCH >= 12 ? 1 : (RREG >= 4 ? 2 : 4)) : 1)))
 search_kernel(SearchParams P) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
@@ -710,8 +711,6 @@ search_kernel(SearchParams P) {
                 if (to_trace == 0) to_trace = P.trace_interval;
             }
             if (want_stop || want_trace) {
-                MlpRegs M{};
-                if (want_stop) M = mlp_load(P.stop_w);  // in flight while the features are formed
                 // lane i < 16 computes state feature i from the wave-uniform state:
                 // sqrt of a count, a ratio (correctly rounded), or a plain value
                 const int kq = min(k, rcnt);
@@ -792,7 +791,8 @@ search_kernel(SearchParams P) {
                 }
                 if (want_stop) {
                     const float fs = lane < NFEAT ? __fmul_rn(__fsub_rn(fv, f_mean), f_istd) : 0.0f;
-                    const float z = mlp_logit(M, P.stop_w, fs, hbuf);
+                    // the weights are read here, not held across hops
+                    const float z = mlp_logit(mlp_load(P.stop_w), P.stop_w, fs, hbuf);
                     if (z >= (hops >= P.stop_long_hops ? P.stop_tau_long : P.stop_tau)) {
                         flags |= DEG_FLAG_LEARNED_STOP;
                         break;
