@@ -135,7 +135,8 @@ typedef struct {
     int32_t hash_slots; /* LDS visited-table slots (power of 2, 256..16384); 0 = the tuned
                            value if one is registered, else 512. At 3/4 load the set moves
                            to a workspace table, and from there to one four times larger
-                           at each 3/4 load (the last holds all n vertices). */
+                           at each 3/8 load (the last, shared, holds all n vertices
+                           below 3/4 load). */
     int32_t k_pool;     /* traversal result size (>= k); the pool is reranked in FP32
                            from f32_data when k_pool > k or dtype != DEG_F32; 0 = k */
     int32_t rerank;     /* 1 = always rerank the pool in FP32, 0 = only when needed */

@@ -20,10 +20,11 @@ __global__ void reset_kernel(int32_t *counter, int32_t *owners, int npool) {
     for (int i = (int)threadIdx.x; i < npool; i += (int)blockDim.x) owners[i] = 0;
 }
 
-// Workspace visited tables: the first holds 8192 slots (32 KiB), a wave's own
+// Workspace visited tables: the first holds 16384 slots (64 KiB), a wave's own
 // region goes up to 131072 slots (512 KiB), and larger sets take one of up
-// to 64 shared tables sized for all n vertices.
-constexpr int HG_FIRST = 8192;
+// to 64 shared tables sized for all n vertices. A private table is left at
+// 3/8 load, so that most probes end within the eight slots of one read.
+constexpr int HG_FIRST = 16384;
 // S: capacity 16384 by default (at these sizes no search holds that many live
 // candidates, so the result is Algorithm 1's exactly), 512 keys of it in LDS.
 constexpr int DEFAULT_L = 16384;

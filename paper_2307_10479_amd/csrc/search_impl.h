@@ -65,32 +65,6 @@ __device__ __forceinline__ int b_drop_dead(uint64_t *B, int n, float thr) {
     return out;
 }
 
-// The same for G, in the wave's workspace: four chunks of 64 keys are loaded
-// before any is written back (the writes only go to positions already read),
-// so that the loads of a round overlap instead of waiting one by one.
-__device__ __forceinline__ int g_drop_dead(uint64_t *G, int n, float thr) {
-    const int lane = lane_id();
-    const uint32_t othr = ord_of(thr);
-    int out = 0;
-    for (int base = 0; base < n; base += 4 * WAVE) {
-        uint64_t v[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = base + u * WAVE + lane;
-            v[u] = i < n ? G[i] : KEY_MAX;
-        }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = base + u * WAVE + lane;
-            const bool keep = i < n && (uint32_t)(v[u] >> 32) <= othr;
-            const uint64_t m = ballot(keep);
-            if (keep) G[out + prefix_in(m)] = v[u];
-            out += __popcll(m);
-        }
-    }
-    return out;
-}
-
 // The k-th smallest (1 <= k <= n) of the n distinct keys in B (LDS or this
 // wave's workspace): each round splits the current key range into 64
 // power-of-two buckets, counts them with LDS atomics and keeps the bucket that
@@ -187,36 +161,14 @@ __device__ __forceinline__ void f_from_stage(SQueue &S, int c) {
     wave_sync();
 }
 
-// B is empty: it takes back the smallest live keys of G (up to half its capacity;
-// usually most keys of G are dead by then and all live ones fit).
+// B is empty: it takes back the smallest live keys of G (up to half its capacity).
 __device__ __forceinline__ void b_from_g(SQueue &S, float thr) {
-    S.gcnt = g_drop_dead(S.G, S.gcnt, thr);
+    S.gcnt = b_drop_dead(S.G, S.gcnt, thr);
     if (S.gcnt == 0) {
         S.phi = KEY_MAX;
         return;
     }
     const int want = S.bcap / 2;
-    if (S.gcnt <= want) {
-        const int lane = lane_id();
-        for (int base = 0; base < S.gcnt; base += 4 * WAVE) {
-            uint64_t v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = base + u * WAVE + lane;
-                v[u] = i < S.gcnt ? S.G[i] : KEY_MAX;
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int i = base + u * WAVE + lane;
-                if (i < S.gcnt) S.B[i] = v[u];
-            }
-        }
-        wave_sync();
-        S.bcnt = S.gcnt;
-        S.gcnt = 0;
-        S.phi = KEY_MAX;
-        return;
-    }
     const uint64_t T = S.gcnt <= want ? KEY_MAX : b_kth(S.G, S.gcnt, want, S.stage, S.hist);
     // keys <= T go to B, the rest stay in G
     int moved = 0;
@@ -376,7 +328,7 @@ __device__ __forceinline__ CutOut s_cut(uint64_t f, int fcnt, uint64_t *B, int b
     f = lane < fl ? f : KEY_MAX;
     fcnt = fl;
     bcnt = b_drop_dead(B, bcnt, thr);
-    gcnt = g_drop_dead(G, gcnt, thr);
+    gcnt = b_drop_dead(G, gcnt, thr);
     if (fcnt + bcnt + gcnt > L) {
         o.dropped = true;
         if (fcnt + bcnt < L) {
@@ -639,10 +591,11 @@ search_kernel(SearchParams P) {
         int n_acc_s = 0, n_acc_r = 0;
         int nrow = 0;
         int to_stop = P.stop_interval, to_trace = P.trace_interval;  // hops until the next checkpoint
-        // adjacency rows requested ahead for the likely next pop: the runner-up in
-        // S at the previous pop (the next pop in about nine hops of ten) and the
-        // closest new candidate of the previous hop
-        int32_t run_v = -1, run_nb = -1, spec_v = -1, spec_nb = -1;
+        // adjacency rows requested ahead: run_v is the smallest key of S after the
+        // previous pop (the next pop in about nine hops of ten), nxt_v the one after
+        // it (usually run_v of the next hop: its row is requested a hop early), and
+        // spec_v the closest new candidate of the previous hop
+        int32_t run_v = -1, run_nb = -1, spec_v = -1, spec_nb = -1, nxt_v = -1, nxt_nb = -1;
         // workspace-table slots of run_v's neighbours, read during the previous hop
         // (after its claims) for the probe of the next pop if that is run_v
         int32_t pv = -1;
@@ -802,10 +755,24 @@ search_kernel(SearchParams P) {
 
             // N <- N(G,s) \ C ; C <- C u N
             const int32_t s = key_id(gmin);
-            int32_t nb = -1;
-            if (lane < deg)
-                nb = s == run_v ? run_nb : (s == spec_v ? spec_nb : P.adj[(int64_t)s * P.astride + lane]);
-            run_v = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
+            // (uniform branches: only the row used is waited for)
+            int32_t nb;
+            if (s == run_v) nb = run_nb;
+            else if (s == nxt_v) nb = nxt_nb;
+            else if (s == spec_v) nb = spec_nb;
+            else nb = lane < deg ? P.adj[(int64_t)s * P.astride + lane] : -1;
+            if (lane >= deg) nb = -1;
+            // the likely next pop and its row, if requested before (early: a hop ago
+            // or more, so it has arrived; the row of a candidate that took the lead
+            // in the previous hop was requested at its end and may still be in flight)
+            const int32_t rv = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
+            const bool early = rv >= 0 && (rv == nxt_v || rv == run_v);
+            const bool have_row = early || (rv >= 0 && rv == spec_v);
+            if (rv >= 0 && rv != run_v) {
+                if (rv == nxt_v) run_nb = nxt_nb;
+                else if (rv == spec_v) run_nb = spec_nb;
+            }
+            run_v = rv;
             // (its lanes below the degree are read only when the next pop is run_v)
             const int32_t *pf = P.adj + ((run_v >= 0 && lane < deg) ? (int64_t)run_v * P.astride + lane : 0);
             const bool bad = lane < deg && (nb < 0 || (int64_t)nb >= P.n);
@@ -820,18 +787,21 @@ search_kernel(SearchParams P) {
             bool isnew;
             if (V.spilled && s == pv && V.gtab == pv_tab) {
                 // the first probe round was read ahead: no table round trip here
-                run_nb = *pf;
+                if (!have_row) run_nb = *pf;
                 int32_t unused = 0;
                 isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
                                                    hash_slot(nb, V.hgshift), nb, nb >= 0, nullptr,
                                                    unused, pa, pb);
+            } else if (have_row) {
+                isnew = visit_insert(V, nb, nb >= 0);
             } else {
-                // the runner-up's row is requested inside the check, after its table reads
+                // the next pop's row is requested inside the check, after its table reads
                 isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
             }
-            // read ahead the table slots of run_v's neighbours (run_v is the next pop
-            // in about nine hops of ten): issued after this hop's claims, so nothing
-            // is inserted between these reads and their use
+            // read ahead the table slots of run_v's neighbours for the next hop's
+            // check: issued after this hop's claims, so nothing is inserted between
+            // these reads and their use; right away when run_v's row is at hand,
+            // else once this hop's rows are in
             auto spec = [&]() {
                 if (V.spilled && run_v >= 0) {
                     spec_read(V, run_nb, lane < deg && run_nb >= 0 && (int64_t)run_nb < P.n, pa, pb);
@@ -841,6 +811,13 @@ search_kernel(SearchParams P) {
                     pv = -1;
                 }
             };
+            if (early) spec();
+            // the pop after run_v: its row is requested now, for the next hop
+            const int32_t nv = S.fcnt > 1 ? key_id(read_lane_u64(S.f, 1)) : -1;
+            if (nv != nxt_v) {
+                nxt_v = nv;
+                nxt_nb = (nv >= 0 && lane < deg) ? P.adj[(int64_t)nv * P.astride + lane] : -1;
+            }
             const uint64_t nm = ballot(isnew);
             const int cnt = __popcll(nm);
             V.count += cnt;
@@ -848,17 +825,12 @@ search_kernel(SearchParams P) {
             n_acc_s = 0;
             n_acc_r = 0;
             if (cnt == 0) {
-                spec();
+                if (!early) spec();
                 continue;
             }
-            // the table reads go out once the new rows are in
             const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb);
-            spec();
+            if (!early) spec();
             const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
-
-            // the closest new candidate is the likely next pop: load its row now
-            spec_v = key_id(wave_min_u64(ck));
-            spec_nb = lane < deg ? P.adj[(int64_t)spec_v * P.astride + lane] : -1;
 
             // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
             const uint64_t old_first = read_lane_u64(R[0], 0);
@@ -881,6 +853,16 @@ search_kernel(SearchParams P) {
             n_acc_r = na;
             if (np > 0) s_push(S, ck, pm, thr);
             if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
+            // a new candidate that now leads S is the next pop: its row is requested
+            // here (the only read left in flight at the end of a hop, so the next
+            // hop's first waits need not include it otherwise)
+            if (np > 0 && S.fcnt > 0) {
+                const int32_t lead = key_id(read_lane_u64(S.f, 0));
+                if (lead != run_v && lead != nxt_v && lead != spec_v) {
+                    spec_v = lead;
+                    spec_nb = lane < deg ? P.adj[(int64_t)lead * P.astride + lane] : -1;
+                }
+            }
         }
 
         pool_give(V, P);  // a shared visited table goes back at the end of the query

@@ -471,10 +471,10 @@ __device__ __forceinline__ float batch_dist(const SearchParams &P, const float4 
 // ---------------------------------------------------------------- visited set
 // Visited set C of one query, exact for any number of checked vertices. It
 // starts in an LDS hash table; when that is 3/4 full every id moves to the
-// first table of the wave's workspace region, and each time a workspace table
-// is 3/4 full the ids move to one four times larger (the next table of the
-// region, or a shared table of hg_cap slots, which holds all n vertices below
-// 3/4 load).
+// first table of the wave's workspace region, and each time a private
+// workspace table is 3/8 full the ids move to one four times larger (the next
+// table of the region, or a shared table of hg_cap slots, which holds all n
+// vertices below 3/4 load).
 struct Visited {
     int32_t *htab;  // LDS
     int32_t *region;// the wave's workspace region
@@ -698,7 +698,7 @@ __device__ __forceinline__ void table_use(Visited &V, int32_t *t, int slots, int
     V.gtab = t;
     V.Hg = slots;
     V.hgshift = 32 - ilog2_dev(slots);
-    V.limit = slots >= hg_cap ? 0x7fffffff : (3 * slots) / 4;
+    V.limit = slots >= hg_cap ? 0x7fffffff : (3 * slots) / 8;
 }
 
 // Moves the LDS table to the first table of the region (cleared first).
