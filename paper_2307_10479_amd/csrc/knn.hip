@@ -123,6 +123,47 @@ __device__ uint64_t cut_list(uint64_t *buf, int &cnt, int kc) {
     return ans;
 }
 
+// cut_list with the list held in registers (R keys per lane, cnt <= 64 R): the
+// same bit-by-bit construction of the kc-th key, counting with ballots instead
+// of a pass over memory per bit.
+template <int R>
+__device__ uint64_t cut_list_regs(uint64_t *buf, int &cnt, int kc) {
+    const int lane = lane_id();
+    uint64_t v[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int i = r * WAVE + lane;
+        v[r] = i < cnt ? buf[i] : KEY_MAX;
+    }
+    uint64_t ans = 0;
+    for (int b = 63; b >= 0; --b) {
+        const uint64_t cand = ans | (1ull << b);
+        int c = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) c += __popcll(ballot(v[r] < cand));
+        if (c < kc) ans = cand;
+    }
+    int out = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool keep = r * WAVE + lane < cnt && v[r] <= ans;
+        const uint64_t m = ballot(keep);
+        if (keep) buf[out + prefix_in(m)] = v[r];
+        out += __popcll(m);
+    }
+    __threadfence_block();
+    cnt = out;
+    return ans;
+}
+
+__device__ __forceinline__ uint64_t cut_any(uint64_t *buf, int &cnt, int kc, int cap) {
+    if (cap <= 4 * WAVE) return cut_list_regs<4>(buf, cnt, kc);
+    if (cap <= 7 * WAVE) return cut_list_regs<7>(buf, cnt, kc);
+    if (cap <= 16 * WAVE) return cut_list_regs<16>(buf, cnt, kc);
+    if (cap <= 36 * WAVE) return cut_list_regs<36>(buf, cnt, kc);
+    return cut_list(buf, cnt, kc);
+}
+
 // Tile kernel. Wave w computes queries 64 (w >> 1) + [0, 64) against base rows
 // 64 (w & 1) + [0, 64) of the tile as 2 x 2 blocks of 32 x 32; in a block's
 // accumulator, lane l register v holds row 8 (v / 4) + 4 (l / 32) + v % 4 and
@@ -377,7 +418,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
             int c = rcnt[row];
             if (c > P.cap - KN && q0 + row < P.nq) {
                 uint64_t *lst = P.lists + ((q0 + row) * P.nslices + slice) * P.cap;
-                const uint64_t th = cut_list(lst, c, P.kc);
+                const uint64_t th = cut_any(lst, c, P.kc, P.cap);
                 if (lane == 0) {
                     rcnt[row] = c;
                     rthr[row] = key_dist(th);
@@ -394,7 +435,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
         if (qi >= P.nq) break;
         int c = rcnt[row];
         uint64_t *lst = P.lists + (qi * P.nslices + slice) * P.cap;
-        if (c > P.kc) cut_list(lst, c, P.kc);
+        if (c > P.kc) cut_any(lst, c, P.kc, P.cap);
         if (lane == 0) P.counts[qi * P.nslices + slice] = c;
     }
 }
