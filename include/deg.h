@@ -159,8 +159,9 @@ typedef struct {
 /*
  * Workspace bytes needed by deg_search / deg_search_indexed / deg_search_batch
  * for `nq` queries with results of size up to `k` and these options: a work
- * counter, one region of visited tables per resident wave (8192 slots, then
- * four times larger up to 131072) and, when n needs larger tables, up to 64
+ * counter, one region of visited tables per resident wave (16384 slots, then
+ * four times larger up to 262144), S's far part (L + 256 keys per resident
+ * wave) and, when n needs larger tables, up to 64
  * shared tables of the smallest power of two >= 4n/3 int32 slots (a query
  * that needs one while all are held waits for one). Concurrent calls must not
  * share a workspace.

@@ -21,15 +21,17 @@ __global__ void reset_kernel(int32_t *counter, int32_t *owners, int npool) {
 }
 
 // Workspace visited tables: the first holds 16384 slots (64 KiB), a wave's own
-// region goes up to 131072 slots (512 KiB), and larger sets take one of up
-// to 64 shared tables sized for all n vertices. A private table is left at
-// 3/8 load, so that most probes end within the eight slots of one read.
+// region chains 16384, 65536 and 262144 slots (1.3 MiB), and larger sets take
+// one of up to 64 shared tables sized for all n vertices (a query that needs
+// one waits while all are held, so they are for the rare very long search). A
+// private table is left at 3/8 load, so that most probes end within the eight
+// slots of one read.
 constexpr int HG_FIRST = 16384;
 // S: capacity 16384 by default (at these sizes no search holds that many live
 // candidates, so the result is Algorithm 1's exactly), 512 keys of it in LDS.
 constexpr int DEFAULT_L = 16384;
 constexpr int DEFAULT_BCAP = 512;
-constexpr int HG_PRIV_MAX = 131072;
+constexpr int HG_PRIV_MAX = 262144;
 constexpr int POOL_MAX = 64;
 
 static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, bool feat) {
