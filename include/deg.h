@@ -80,7 +80,10 @@ typedef struct {
 /*
  * The graph: n rows of `row_stride` int32 neighbour ids, the first `degree`
  * of which are the vertex's neighbours (Sec. 5.4: search reads ids only, no
- * edge weights). degree must be even and >= 4 (Sec. 5.1) and <= 64.
+ * edge weights). degree must be even and >= 4 (Sec. 5.1) and <= 128 (a row of
+ * more than 64 neighbours is expanded in two parts of up to 64; such graphs take
+ * pools of up to 256, up to 512 dims and no learned stop or trace rows, else
+ * DEG_ERR_UNSUPPORTED).
  */
 typedef struct {
     const int32_t *adj;

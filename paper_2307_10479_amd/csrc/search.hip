@@ -34,11 +34,11 @@ constexpr int DEFAULT_BCAP = 512;
 constexpr int HG_PRIV_MAX = 262144;
 constexpr int POOL_MAX = 64;
 
-static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, bool feat) {
+static KernelFn pick_kernel(int dt, int metric, int qch, int rreg, int mode) {
     switch (dt) {
-        case DT_F32: return pick_kernel_f32(metric, qch, rreg, feat);
-        case DT_BF16: return pick_kernel_bf16(metric, qch, rreg, feat);
-        default: return pick_kernel_fp8(metric, qch, rreg, feat);
+        case DT_F32: return pick_kernel_f32(metric, qch, rreg, mode);
+        case DT_BF16: return pick_kernel_bf16(metric, qch, rreg, mode);
+        default: return pick_kernel_fp8(metric, qch, rreg, mode);
     }
 }
 
@@ -99,13 +99,17 @@ static deg_status validate_common(const deg_vectors *v, const deg_graph *g, int3
     if (v->metric != DEG_METRIC_L2 && v->metric != DEG_METRIC_IP) return DEG_ERR_INVALID_ARG;
     if (v->dtype == DEG_FP8_E4M3 && !v->scale) return DEG_ERR_INVALID_ARG;
     if (((v->dim + 3) / 4 + 31) / 32 > 12) return DEG_ERR_UNSUPPORTED;
-    if (g->degree < 4 || (g->degree & 1) || g->degree > 64 || g->row_stride < g->degree)
+    if (g->degree < 4 || (g->degree & 1) || g->degree > 128 || g->row_stride < g->degree)
         return DEG_ERR_INVALID_ARG;
+    // the stop features count a row as one batch: rows of up to one wave
+    if (g->degree > 64 && o && (o->stop || o->trace)) return DEG_ERR_UNSUPPORTED;
     if (kmax < 1 || kmax > 1024) return DEG_ERR_INVALID_ARG;
     int kp = kmax;
     if (o && o->k_pool > kp) kp = o->k_pool;
     if (kp > 1024) return DEG_ERR_INVALID_ARG;
     if (kp > 512 && o && (o->stop || o->trace)) return DEG_ERR_UNSUPPORTED;  // stop features: k <= 512
+    // rows longer than a wave: kernels for pools of up to 256 and up to 512 dims
+    if (g->degree > 64 && (kp > 256 || ((v->dim + 3) / 4 + 31) / 32 > 4)) return DEG_ERR_UNSUPPORTED;
     bool rerank = v->dtype != DEG_F32 || (o && (o->rerank || o->k_pool > kmax));
     if ((rerank || need_f32) && !v->f32_data) return DEG_ERR_INVALID_ARG;
     if (v->f32_data && (v->f32_stride < v->dim || (v->f32_stride & 3))) return DEG_ERR_INVALID_ARG;
@@ -149,7 +153,7 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     c.hshift = 32 - ilog2(H);
     c.lds = 4 * (size_t)H + 8 * (size_t)c.scap + 8 * 128 + 8 * 64 * (size_t)c.rreg + 4 * 64 + 4 * 64;
     const bool feat = o && (o->stop || o->trace);
-    c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg, feat);
+    c.fn = pick_kernel(v->dtype, v->metric, c.qch, c.rreg, feat ? 1 : (g->degree > 64 ? 2 : 0));
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(c.fn), 64,
                                                      c.lds) != hipSuccess || nb < 1)
@@ -167,7 +171,7 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
 
 static deg_status launch(const LaunchCfg &c, SearchParams &P, void *ws, size_t ws_bytes,
                          hipStream_t st) {
-    if (c.lds > 64 * 1024) return DEG_ERR_UNSUPPORTED;
+    if (c.lds > 64 * 1024 || c.fn == nullptr) return DEG_ERR_UNSUPPORTED;
     if (ws_bytes < c.ws_bytes || !ws) return DEG_ERR_WORKSPACE;
     char *w = reinterpret_cast<char *>(ws);
     P.counter = reinterpret_cast<int32_t *>(w);

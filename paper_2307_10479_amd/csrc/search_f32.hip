@@ -2,7 +2,7 @@
 #include "search_impl.h"
 
 namespace degk {
-KernelFn pick_kernel_f32(int metric, int qch, int rreg, bool feat) {
-    return pick_m<DT_F32>(metric, qch, rreg, feat);
+KernelFn pick_kernel_f32(int metric, int qch, int rreg, int mode) {
+    return pick_m<DT_F32>(metric, qch, rreg, mode);
 }
 }  // namespace degk

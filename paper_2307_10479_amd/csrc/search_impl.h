@@ -443,9 +443,13 @@ __device__ __forceinline__ bool r_merge(uint64_t (&R)[RREG], int &rcnt, int &tot
 // result registers it is held to 128 VGPRs (four waves per SIMD; the few spills
 // fall outside the hop loop), with more to 256 (two), and wide rows (QCH 12)
 // are left to the compiler.
-template <int DT, int METRIC, int QCH, int RREG, bool FEAT>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(FEAT ? (QCH >= 12 ? 1 : (RREG >= 4 ? 2 : 4)) : 1)))
+// MODE: 0 the plain search, 1 with the stop features (learned stop, trace rows),
+// 2 the plain search on rows of up to 128 neighbours (two parts per hop).
+template <int DT, int METRIC, int QCH, int RREG, int MODE>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(MODE == 1 ? (QCH >= 12 ? 1 : (RREG >= 4 ? 2 : 4)) : 1)))
 search_kernel(SearchParams P) {
+    constexpr bool FEAT = MODE == 1;
+    constexpr int MAX_PARTS = MODE == 2 ? 2 : 1;
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = lane_id();
     const int p = lane & 31;
@@ -753,114 +757,246 @@ search_kernel(SearchParams P) {
                 }
             }
 
-            // N <- N(G,s) \ C ; C <- C u N
-            const int32_t s = key_id(gmin);
-            // (uniform branches: only the row used is waited for)
-            int32_t nb;
-            if (s == run_v) nb = run_nb;
-            else if (s == nxt_v) nb = nxt_nb;
-            else if (s == spec_v) nb = spec_nb;
-            else nb = lane < deg ? P.adj[(int64_t)s * P.astride + lane] : -1;
-            if (lane >= deg) nb = -1;
-            // the likely next pop and its row, if requested before (early: a hop ago
-            // or more, so it has arrived; the row of a candidate that took the lead
-            // in the previous hop was requested at its end and may still be in flight)
-            const int32_t rv = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
-            const bool early = rv >= 0 && (rv == nxt_v || rv == run_v);
-            const bool have_row = early || (rv >= 0 && rv == spec_v);
-            if (rv >= 0 && rv != run_v) {
-                if (rv == nxt_v) run_nb = nxt_nb;
-                else if (rv == spec_v) run_nb = spec_nb;
-            }
-            run_v = rv;
-            // (its lanes below the degree are read only when the next pop is run_v)
-            const int32_t *pf = P.adj + ((run_v >= 0 && lane < deg) ? (int64_t)run_v * P.astride + lane : 0);
-            const bool bad = lane < deg && (nb < 0 || (int64_t)nb >= P.n);
-            if (bad) nb = -1;
-            if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
-            if (!V.spilled && V.count + deg > hlimit) {
-                visit_spill(V, P);
-                flags |= DEG_FLAG_HASH_SPILL;
-            } else if (V.spilled && V.count + deg > V.limit) {
-                visit_grow(V, P);
-            }
-            bool isnew;
-            if (V.spilled && s == pv && V.gtab == pv_tab) {
-                // the first probe round was read ahead: no table round trip here
-                if (!have_row) run_nb = *pf;
-                int32_t unused = 0;
-                isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
-                                                   hash_slot(nb, V.hgshift), nb, nb >= 0, nullptr,
-                                                   unused, pa, pb);
-            } else if (have_row) {
-                isnew = visit_insert(V, nb, nb >= 0);
-            } else {
-                // the next pop's row is requested inside the check, after its table reads
-                isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
-            }
-            // read ahead the table slots of run_v's neighbours for the next hop's
-            // check: issued after this hop's claims, so nothing is inserted between
-            // these reads and their use; right away when run_v's row is at hand,
-            // else once this hop's rows are in
-            auto spec = [&]() {
-                if (V.spilled && run_v >= 0) {
-                    spec_read(V, run_nb, lane < deg && run_nb >= 0 && (int64_t)run_nb < P.n, pa, pb);
-                    pv = run_v;
-                    pv_tab = V.gtab;
-                } else {
-                    pv = -1;
+            if constexpr (MAX_PARTS == 1) {
+                // N <- N(G,s) \ C ; C <- C u N
+                const int32_t s = key_id(gmin);
+                // (uniform branches: only the row used is waited for)
+                int32_t nb;
+                if (s == run_v) nb = run_nb;
+                else if (s == nxt_v) nb = nxt_nb;
+                else if (s == spec_v) nb = spec_nb;
+                else nb = lane < deg ? P.adj[(int64_t)s * P.astride + lane] : -1;
+                if (lane >= deg) nb = -1;
+                // the likely next pop and its row, if requested before (early: a hop ago
+                // or more, so it has arrived; the row of a candidate that took the lead
+                // in the previous hop was requested at its end and may still be in flight)
+                const int32_t rv = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
+                const bool early = rv >= 0 && (rv == nxt_v || rv == run_v);
+                const bool have_row = early || (rv >= 0 && rv == spec_v);
+                if (rv >= 0 && rv != run_v) {
+                    if (rv == nxt_v) run_nb = nxt_nb;
+                    else if (rv == spec_v) run_nb = spec_nb;
                 }
-            };
-            if (early) spec();
-            // the pop after run_v: its row is requested now, for the next hop
-            const int32_t nv = S.fcnt > 1 ? key_id(read_lane_u64(S.f, 1)) : -1;
-            if (nv != nxt_v) {
-                nxt_v = nv;
-                nxt_nb = (nv >= 0 && lane < deg) ? P.adj[(int64_t)nv * P.astride + lane] : -1;
-            }
-            const uint64_t nm = ballot(isnew);
-            const int cnt = __popcll(nm);
-            V.count += cnt;
-            evals += cnt;
-            n_acc_s = 0;
-            n_acc_r = 0;
-            if (cnt == 0) {
+                run_v = rv;
+                // (its lanes below the degree are read only when the next pop is run_v)
+                const int32_t *pf = P.adj + ((run_v >= 0 && lane < deg) ? (int64_t)run_v * P.astride + lane : 0);
+                const bool bad = lane < deg && (nb < 0 || (int64_t)nb >= P.n);
+                if (bad) nb = -1;
+                if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
+                if (!V.spilled && V.count + deg > hlimit) {
+                    visit_spill(V, P);
+                    flags |= DEG_FLAG_HASH_SPILL;
+                } else if (V.spilled && V.count + deg > V.limit) {
+                    visit_grow(V, P);
+                }
+                bool isnew;
+                if (V.spilled && s == pv && V.gtab == pv_tab) {
+                    // the first probe round was read ahead: no table round trip here
+                    if (!have_row) run_nb = *pf;
+                    int32_t unused = 0;
+                    isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
+                                                       hash_slot(nb, V.hgshift), nb, nb >= 0, nullptr,
+                                                       unused, pa, pb);
+                } else if (have_row) {
+                    isnew = visit_insert(V, nb, nb >= 0);
+                } else {
+                    // the next pop's row is requested inside the check, after its table reads
+                    isnew = visit_insert<true>(V, nb, nb >= 0, pf, run_nb);
+                }
+                // read ahead the table slots of run_v's neighbours for the next hop's
+                // check: issued after this hop's claims, so nothing is inserted between
+                // these reads and their use; right away when run_v's row is at hand,
+                // else once this hop's rows are in
+                auto spec = [&]() {
+                    if (V.spilled && run_v >= 0) {
+                        spec_read(V, run_nb, lane < deg && run_nb >= 0 && (int64_t)run_nb < P.n, pa, pb);
+                        pv = run_v;
+                        pv_tab = V.gtab;
+                    } else {
+                        pv = -1;
+                    }
+                };
+                if (early) spec();
+                // the pop after run_v: its row is requested now, for the next hop
+                const int32_t nv = S.fcnt > 1 ? key_id(read_lane_u64(S.f, 1)) : -1;
+                if (nv != nxt_v) {
+                    nxt_v = nv;
+                    nxt_nb = (nv >= 0 && lane < deg) ? P.adj[(int64_t)nv * P.astride + lane] : -1;
+                }
+                const uint64_t nm = ballot(isnew);
+                const int cnt = __popcll(nm);
+                V.count += cnt;
+                evals += cnt;
+                n_acc_s = 0;
+                n_acc_r = 0;
+                if (cnt == 0) {
+                    if (!early) spec();
+                    continue;
+                }
+                const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb);
                 if (!early) spec();
-                continue;
-            }
-            const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nb, nm, nch, mask_tail, xb);
-            if (!early) spec();
-            const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
+                const uint64_t ck = isnew ? make_key(cd, nb) : KEY_MAX;
 
-            // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
-            const uint64_t old_first = read_lane_u64(R[0], 0);
-            int na;
-            uint64_t rm = ballot(isnew && nb != vtx);
-            if (nex > 0) rm &= ~excluded_lanes(exl, nex, nb, rm & ballot(cd <= r));
-            const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, rm, mbuf, t10, na);
-            if (chg) last_chg = hops;
-            if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
-            const float r_old = r;
-            r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
-            if (r != r_old) last_r = hops;
+                // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
+                const uint64_t old_first = read_lane_u64(R[0], 0);
+                int na;
+                uint64_t rm = ballot(isnew && nb != vtx);
+                if (nex > 0) rm &= ~excluded_lanes(exl, nex, nb, rm & ballot(cd <= r));
+                const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, rm, mbuf, t10, na);
+                if (chg) last_chg = hops;
+                if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
+                const float r_old = r;
+                r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
+                if (r != r_old) last_r = hops;
 
-            // S <- S u {n : delta(n,q) <= r (1 + eps)}
-            const float thr = thr_of(r, onep);
-            const bool push = isnew && cd <= thr;
-            const uint64_t pm = ballot(push);
-            const int np = __popcll(pm);
-            n_acc_s = np;
-            n_acc_r = na;
-            if (np > 0) s_push(S, ck, pm, thr);
-            if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
-            // a new candidate that now leads S is the next pop: its row is requested
-            // here (the only read left in flight at the end of a hop, so the next
-            // hop's first waits need not include it otherwise)
-            if (np > 0 && S.fcnt > 0) {
-                const int32_t lead = key_id(read_lane_u64(S.f, 0));
-                if (lead != run_v && lead != nxt_v && lead != spec_v) {
-                    spec_v = lead;
-                    spec_nb = lane < deg ? P.adj[(int64_t)lead * P.astride + lane] : -1;
+                // S <- S u {n : delta(n,q) <= r (1 + eps)}
+                const float thr = thr_of(r, onep);
+                const bool push = isnew && cd <= thr;
+                const uint64_t pm = ballot(push);
+                const int np = __popcll(pm);
+                n_acc_s = np;
+                n_acc_r = na;
+                if (np > 0) s_push(S, ck, pm, thr);
+                if (s_capacity(S, thr, P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
+                // a new candidate that now leads S is the next pop: its row is requested
+                // here (the only read left in flight at the end of a hop, so the next
+                // hop's first waits need not include it otherwise)
+                if (np > 0 && S.fcnt > 0) {
+                    const int32_t lead = key_id(read_lane_u64(S.f, 0));
+                    if (lead != run_v && lead != nxt_v && lead != spec_v) {
+                        spec_v = lead;
+                        spec_nb = lane < deg ? P.adj[(int64_t)lead * P.astride + lane] : -1;
+                    }
+                }
+            } else {
+                // N <- N(G,s) \ C ; C <- C u N
+                const int32_t s = key_id(gmin);
+                // (uniform branches: only the row used is waited for)
+                int32_t nb;
+                if (s == run_v) nb = run_nb;
+                else if (s == nxt_v) nb = nxt_nb;
+                else if (s == spec_v) nb = spec_nb;
+                else nb = lane < deg ? P.adj[(int64_t)s * P.astride + lane] : -1;
+                if (lane >= deg) nb = -1;
+                // a row longer than a wave is expanded in two parts of up to 64
+                // neighbours (a batch per part; the result does not depend on the
+                // grouping, see the order independence of a row); the second part is
+                // requested now
+                const int nparts = (MAX_PARTS == 2 && deg > WAVE) ? 2 : 1;
+                int32_t nb2 = -1;
+                if (nparts == 2) nb2 = lane + WAVE < deg ? P.adj[(int64_t)s * P.astride + WAVE + lane] : -1;
+                // the likely next pop and its row, if requested before (early: a hop ago
+                // or more, so it has arrived; the row of a candidate that took the lead
+                // in the previous hop was requested at its end and may still be in flight)
+                const int32_t rv = S.fcnt > 0 ? key_id(read_lane_u64(S.f, 0)) : -1;
+                const bool early = rv >= 0 && (rv == nxt_v || rv == run_v);
+                const bool have_row = early || (rv >= 0 && rv == spec_v);
+                if (rv >= 0 && rv != run_v) {
+                    if (rv == nxt_v) run_nb = nxt_nb;
+                    else if (rv == spec_v) run_nb = spec_nb;
+                }
+                run_v = rv;
+                // (its lanes below the degree are read only when the next pop is run_v)
+                const int32_t *pf = P.adj + ((run_v >= 0 && lane < deg) ? (int64_t)run_v * P.astride + lane : 0);
+                // read ahead the table slots of run_v's neighbours (its first 64) for the
+                // next hop's check: issued after this hop's claims, so nothing is
+                // inserted between these reads and their use; right away when run_v's
+                // row is at hand, else once this hop's last rows are in
+                auto spec = [&]() {
+                    if (V.spilled && run_v >= 0) {
+                        spec_read(V, run_nb, lane < deg && run_nb >= 0 && (int64_t)run_nb < P.n, pa, pb);
+                        pv = run_v;
+                        pv_tab = V.gtab;
+                    } else {
+                        pv = -1;
+                    }
+                };
+                n_acc_s = 0;
+                n_acc_r = 0;
+                bool pushed = false;
+                for (int part = 0; part < nparts; ++part) {
+                    const bool last = part == nparts - 1;
+                    int32_t nbp = part == 0 ? nb : nb2;
+                    const bool bad = nbp != -1 && (nbp < 0 || (int64_t)nbp >= P.n);
+                    if (bad) nbp = -1;
+                    if (ballot(bad) != 0) flags |= DEG_FLAG_BAD_ID;
+                    if (!V.spilled && V.count + WAVE > hlimit) {
+                        visit_spill(V, P);
+                        flags |= DEG_FLAG_HASH_SPILL;
+                    } else if (V.spilled && V.count + WAVE > V.limit) {
+                        visit_grow(V, P);
+                    }
+                    bool isnew;
+                    if (part == 0 && V.spilled && s == pv && V.gtab == pv_tab) {
+                        // the first probe round was read ahead: no table round trip here
+                        if (!have_row) run_nb = *pf;
+                        int32_t unused = 0;
+                        isnew = global_insert<false, true>(V.gtab, (uint32_t)V.Hg - 1u,
+                                                           hash_slot(nbp, V.hgshift), nbp, nbp >= 0,
+                                                           nullptr, unused, pa, pb);
+                    } else if (part > 0 || have_row) {
+                        isnew = visit_insert(V, nbp, nbp >= 0);
+                    } else {
+                        // the next pop's row is requested inside the check, after its table reads
+                        isnew = visit_insert<true>(V, nbp, nbp >= 0, pf, run_nb);
+                    }
+                    if (last && early) spec();
+                    if (part == 0) {
+                        // the pop after run_v: its row is requested now, for the next hop
+                        const int32_t nv = S.fcnt > 1 ? key_id(read_lane_u64(S.f, 1)) : -1;
+                        if (nv != nxt_v) {
+                            nxt_v = nv;
+                            nxt_nb = (nv >= 0 && lane < deg) ? P.adj[(int64_t)nv * P.astride + lane] : -1;
+                        }
+                    }
+                    const uint64_t nm = ballot(isnew);
+                    const int cnt = __popcll(nm);
+                    V.count += cnt;
+                    evals += cnt;
+                    if (cnt == 0) {
+                        if (last && !early) spec();
+                        continue;
+                    }
+                    const float cd = batch_dist<DT, METRIC, QCH>(P, qv, nbp, nm, nch, mask_tail, xb);
+                    if (last && !early) spec();
+                    const uint64_t ck = isnew ? make_key(cd, nbp) : KEY_MAX;
+
+                    // R <- top-k of R and the row (Algorithm 1: accepted if delta <= r)
+                    const uint64_t old_first = read_lane_u64(R[0], 0);
+                    int na;
+                    uint64_t rm = ballot(isnew && nbp != vtx);
+                    if (nex > 0) rm &= ~excluded_lanes(exl, nex, nbp, rm & ballot(cd <= r));
+                    const bool chg = r_merge<RREG>(R, rcnt, total, ovf, kp, ck, rm, mbuf, t10, na);
+                    if (chg) last_chg = hops;
+                    if (read_lane_u64(R[0], 0) != old_first) last_d1 = hops;
+                    const float r_old = r;
+                    r = ovf ? key_dist(r_at<RREG>(R, kp - 1)) : __builtin_inff();
+                    if (r != r_old) last_r = hops;
+
+                    // S <- S u {n : delta(n,q) <= r (1 + eps)}
+                    const float thr = thr_of(r, onep);
+                    const bool push = isnew && cd <= thr;
+                    const uint64_t pm = ballot(push);
+                    const int np = __popcll(pm);
+                    n_acc_s += np;
+                    n_acc_r += na;
+                    if (np > 0) {
+                        s_push(S, ck, pm, thr);
+                        pushed = true;
+                    }
+                }
+                // the capacity rule once per hop, at the end-of-row threshold (S grows only
+                // by pushes)
+                if (pushed && s_capacity(S, thr_of(r, onep), P.L)) flags |= DEG_FLAG_QUEUE_OVERFLOW;
+                // a new candidate that now leads S is the next pop: its row is requested
+                // here (the only read left in flight at the end of a hop, so the next
+                // hop's first waits need not include it otherwise)
+                if (pushed && S.fcnt > 0) {
+                    const int32_t lead = key_id(read_lane_u64(S.f, 0));
+                    if (lead != run_v && lead != nxt_v && lead != spec_v) {
+                        spec_v = lead;
+                        spec_nb = lane < deg ? P.adj[(int64_t)lead * P.astride + lane] : -1;
+                    }
                 }
             }
         }
@@ -939,40 +1075,51 @@ search_kernel(SearchParams P) {
 using KernelFn = void (*)(SearchParams);
 
 template <int DT, int METRIC, int QCH>
-static KernelFn pick_r(int rreg, bool feat) {
-    if (feat) {
+static KernelFn pick_r(int rreg, int mode) {
+    if (mode == 1) {
         switch (rreg) {
-            case 1: return search_kernel<DT, METRIC, QCH, 1, true>;
-            case 2: return search_kernel<DT, METRIC, QCH, 2, true>;
-            case 4: return search_kernel<DT, METRIC, QCH, 4, true>;
-            default: return search_kernel<DT, METRIC, QCH, 8, true>;
+            case 1: return search_kernel<DT, METRIC, QCH, 1, 1>;
+            case 2: return search_kernel<DT, METRIC, QCH, 2, 1>;
+            case 4: return search_kernel<DT, METRIC, QCH, 4, 1>;
+            default: return search_kernel<DT, METRIC, QCH, 8, 1>;
         }
     }
+    if (mode == 2) {  // rows longer than a wave: k_pool <= 256 and dim <= 512
+        if constexpr (QCH <= 4) {
+            switch (rreg) {
+                case 1: return search_kernel<DT, METRIC, QCH, 1, 2>;
+                case 2: return search_kernel<DT, METRIC, QCH, 2, 2>;
+                case 4: return search_kernel<DT, METRIC, QCH, 4, 2>;
+                default: return nullptr;
+            }
+        }
+        return nullptr;
+    }
     switch (rreg) {
-        case 1: return search_kernel<DT, METRIC, QCH, 1, false>;
-        case 2: return search_kernel<DT, METRIC, QCH, 2, false>;
-        case 4: return search_kernel<DT, METRIC, QCH, 4, false>;
-        case 8: return search_kernel<DT, METRIC, QCH, 8, false>;
-        default: return search_kernel<DT, METRIC, QCH, 16, false>;
+        case 1: return search_kernel<DT, METRIC, QCH, 1, 0>;
+        case 2: return search_kernel<DT, METRIC, QCH, 2, 0>;
+        case 4: return search_kernel<DT, METRIC, QCH, 4, 0>;
+        case 8: return search_kernel<DT, METRIC, QCH, 8, 0>;
+        default: return search_kernel<DT, METRIC, QCH, 16, 0>;
     }
 }
 template <int DT, int METRIC>
-static KernelFn pick_q(int qch, int rreg, bool feat) {
+static KernelFn pick_q(int qch, int rreg, int mode) {
     switch (qch) {
-        case 1: return pick_r<DT, METRIC, 1>(rreg, feat);
-        case 2: return pick_r<DT, METRIC, 2>(rreg, feat);
-        case 4: return pick_r<DT, METRIC, 4>(rreg, feat);
-        default: return pick_r<DT, METRIC, 12>(rreg, feat);
+        case 1: return pick_r<DT, METRIC, 1>(rreg, mode);
+        case 2: return pick_r<DT, METRIC, 2>(rreg, mode);
+        case 4: return pick_r<DT, METRIC, 4>(rreg, mode);
+        default: return pick_r<DT, METRIC, 12>(rreg, mode);
     }
 }
 template <int DT>
-static KernelFn pick_m(int metric, int qch, int rreg, bool feat) {
-    return metric == DEG_METRIC_L2 ? pick_q<DT, DEG_METRIC_L2>(qch, rreg, feat)
-                                   : pick_q<DT, DEG_METRIC_IP>(qch, rreg, feat);
+static KernelFn pick_m(int metric, int qch, int rreg, int mode) {
+    return metric == DEG_METRIC_L2 ? pick_q<DT, DEG_METRIC_L2>(qch, rreg, mode)
+                                   : pick_q<DT, DEG_METRIC_IP>(qch, rreg, mode);
 }
 
-KernelFn pick_kernel_f32(int metric, int qch, int rreg, bool feat);
-KernelFn pick_kernel_bf16(int metric, int qch, int rreg, bool feat);
-KernelFn pick_kernel_fp8(int metric, int qch, int rreg, bool feat);
+KernelFn pick_kernel_f32(int metric, int qch, int rreg, int mode);
+KernelFn pick_kernel_bf16(int metric, int qch, int rreg, int mode);
+KernelFn pick_kernel_fp8(int metric, int qch, int rreg, int mode);
 
 }  // namespace degk

@@ -292,7 +292,7 @@ __device__ __forceinline__ float half_reduce(float a) {
 template <int DL, int QCH>
 constexpr int dist_rounds_max() {
     constexpr int WPC = DL == DT_F32 ? 4 : (DL == DT_BF16 ? 2 : 1);  // 32-bit words per chunk
-    constexpr int BUDGET = QCH >= 12 ? 96 : 16;
+    constexpr int BUDGET = QCH >= 12 ? 64 : 16;
     constexpr int G0 = BUDGET / (QCH * WPC);
     constexpr int GMAX = QCH >= 12 ? 4 : 8;
     return G0 < 1 ? 1 : (G0 > GMAX ? GMAX : G0);

@@ -365,3 +365,27 @@ def test_parity_exclusion_lists(A, mode):
     assert_parity(got, ref, "exclusion lists %s" % mode)
     for i in range(nq):
         assert not set(got[0][i].tolist()) & set(lists[i])
+
+
+# ---------------------------------------------------------------- rows longer than a wave
+@pytest.mark.parametrize("n,d", [(1000, 80), (600, 128)])
+def test_parity_degree_above_64(A, n, d):
+    """Rows of 80 and 128 neighbours are expanded in two parts of up to 64; ids,
+    distances, hops and evaluations equal the oracle's (which takes the row one
+    neighbour at a time), also with a small capacity of S and for the exploratory
+    search."""
+    say("degree", d, "n", n)
+    x, adj = graph(n, 24, d, "int", seed=11)
+    q = queries_for("int", 12, 40, 24)
+    for k, eps, L in ((10, 0.1, BIG_L), (50, 0.3, BIG_L), (10, 0.2, 24)):
+        ref = oracle.range_search(x, adj, q, [0], k, eps, cap_L=L)
+        got = run_gpu(A, x, adj, q, [[0]] * len(q), k, eps, queue_cap=L)
+        assert_parity(got, ref, "d=%d k=%d eps=%g L=%d" % (d, k, eps, L))
+        assert ((got[2][:, 2] & 1) != 0).tolist() == ((ref[2][:, 3] & 1) != 0).tolist()
+    qids = synth.rng(13).choice(n, size=30, replace=False).astype(np.int32)
+    store = A.VectorStore(dev(x), "f32")
+    G = A.DeviceGraph(dev(adj))
+    ids, ds, st = A.search_indexed(store, G, dev(qids), 20, 0.2, queue_cap=BIG_L)
+    torch.cuda.synchronize()
+    ref = oracle.range_search_indexed(x, adj, qids, 20, 0.2, cap_L=BIG_L)
+    assert_parity((ids.cpu().numpy(), ds.cpu().numpy(), st.cpu().numpy()), ref, "indexed d=%d" % d)

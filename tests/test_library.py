@@ -52,6 +52,8 @@ def test_argument_validation_rejects_before_any_gpu_call(L):
     bad.append(call(v, g))                          # odd degree (Sec. 5.1)
     v, g = _vec_graph(api, degree=2)
     bad.append(call(v, g))                          # degree below 4
+    v, g = _vec_graph(api, degree=130)
+    bad.append(call(v, g))                          # degree above 128 (two parts of a wave)
     v, g = _vec_graph(api)
     bad.append(call(v, g, k=0))                     # k < 1
     bad.append(call(v, g, k=1025))                  # k above the supported maximum (1024)
@@ -69,6 +71,13 @@ def test_argument_validation_rejects_before_any_gpu_call(L):
     assert all(b == 1 for b in bad), bad
     v, g = _vec_graph(api, dim=2000, stride=2000)
     assert call(v, g) == 2                          # dimension beyond the kernels' range
+    # rows longer than a wave: the plain search is accepted, trace rows (stop features)
+    # are not
+    o.trace = 0x400000
+    o.trace_rows_per_query = 4
+    o.trace_interval = 2
+    v, g = _vec_graph(api, degree=80)
+    assert call(v, g) == 2
 
 
 def test_knn_and_mlp_argument_validation(L):
