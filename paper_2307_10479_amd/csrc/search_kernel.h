@@ -2,24 +2,29 @@
 //
 // One wavefront (64 lanes) runs one query at a time; a persistent grid pulls
 // queries from a device counter. Per-wave state:
-//   visited set C   open-addressing int32 hash in LDS (spills to a per-wave
-//                   table in the workspace when 3/4 full), exact
-//   candidates S    unsorted (key) array in LDS with capacity L; keys are
-//                   (orderable distance bits << 32 | id), so one 64-bit
-//                   compare is the (distance, id) order
+//   visited set C   open-addressing int32 hash in LDS; at 3/4 load it moves to
+//                   the wave's workspace tables (16384, 65536, 262144 slots,
+//                   each left at 3/8 load), then to a shared table sized for
+//                   all n vertices: exact for any number of checked vertices
+//   candidates S    keys (orderable distance bits << 32 | id, so one 64-bit
+//                   compare is the (distance, id) order) in three levels: the
+//                   64 smallest sorted across the lanes' registers, the next
+//                   ones unsorted in LDS, the rest in the wave's workspace;
+//                   capacity L
 //   results R       sorted keys in registers, RREG per lane (up to 64*RREG)
-// Each hop expands one row: the adjacency row is read by `degree` lanes, the
-// unchecked ids are compacted with a ballot, and each half-wave computes one
-// distance at a time with 32 partial sums (lane p of the half owns chunks
-// p, p+32, ...), reduced by an xor butterfly that pairs the same partials as
-// the halving tree, so every lane ends with the exact fixed-order sum.
+// Each hop expands one row: the adjacency row is read by `degree` lanes (two
+// parts of up to 64 for longer rows), the unchecked ids are compacted through
+// LDS, and each half-wave computes one distance at a time with 32 partial sums
+// (lane p of the half owns chunks p, p+32, ...), reduced by a swizzle and DPP
+// halving tree that pairs the partials of the fixed order, so the result is the
+// exact fixed-order sum.
 //
-// A row is merged as one batch. This gives the same ids, hops and
-// evaluations as the sequential loop of Algorithm 1: R after a row is the
-// top-k of R plus the row's candidates; a candidate the batch keeps out of S
-// (distance above the end-of-row threshold) could never be expanded, because
-// the radius only shrinks; and entries above the threshold are dropped from S
-// before any live entry is evicted for capacity.
+// A row is merged as one batch (or one batch per part). This gives the same
+// ids, hops and evaluations as the sequential loop of Algorithm 1: R after a
+// row is the top-k of R plus the row's candidates; a candidate the batch keeps
+// out of S (distance above the end-of-row threshold) could never be expanded,
+// because the radius only shrinks; and entries above the threshold are dropped
+// from S before any live entry is evicted for capacity.
 #pragma once
 
 #include <hip/hip_runtime.h>
