@@ -173,6 +173,15 @@ size_t deg_search_workspace_bytes(const deg_vectors *v, const deg_graph *g, int6
                                   int32_t k, const deg_search_opts *o);
 
 /*
+ * Waves per compute unit a search launch with these options keeps resident
+ * (the persistent grid's size per CU when waves_per_cu is 0; a larger request
+ * is capped at it). Launch tuning helper; 0 when the arguments are invalid.
+ * Host-side only (reads the device's occupancy and CU count).
+ */
+int32_t deg_search_resident_waves(const deg_vectors *v, const deg_graph *g, int32_t k,
+                                  const deg_search_opts *o);
+
+/*
  * RangeSearch (Algorithm 1) of nq query vectors, one wavefront per query.
  *   queries   nq rows of q_stride FP32 (dim used)
  *   seed_ids  nq x n_seeds distinct seed vertices (Sec. 5.4: the search starts

@@ -70,7 +70,8 @@ class DegQueryDesc(C.Structure):
 
 
 EXPORTS = [
-    "deg_search_workspace_bytes", "deg_search", "deg_search_noalloc", "deg_search_indexed",
+    "deg_search_workspace_bytes", "deg_search_resident_waves", "deg_search", "deg_search_noalloc",
+    "deg_search_indexed",
     "deg_search_batch",
     "deg_knn_workspace_bytes", "deg_knn_bruteforce", "deg_medoid_workspace_bytes", "deg_medoid",
     "deg_encode_bf16", "deg_encode_fp8", "deg_mlp_workspace_bytes", "deg_mlp_train_step",
@@ -95,6 +96,7 @@ def load_library(path: Path | None = None):
     pv, pg, po = C.POINTER(DegVectors), C.POINTER(DegGraph), C.POINTER(DegSearchOpts)
     sigs = {
         "deg_search_workspace_bytes": (SZ, [pv, pg, I64, I32, po]),
+        "deg_search_resident_waves": (I32, [pv, pg, I32, po]),
         "deg_search": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, P, SZ, V]),
         "deg_search_noalloc": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, V]),
         "deg_search_indexed": (I32, [pv, pg, P, I64, I32, F, po, P, P, P, P, SZ, V]),
@@ -304,6 +306,13 @@ def search_workspace_bytes(store, graph, nq, k, **opts) -> int:
     return int(lib().deg_search_workspace_bytes(C.byref(v), C.byref(g), nq, k, C.byref(o)))
 
 
+def resident_waves_per_cu(store, graph, k, k_pool=0, hash_slots=0, **opts) -> int:
+    """Waves per CU a search launch with these options keeps resident."""
+    o, _keep = _opts(k_pool=k_pool, hash_slots=hash_slots, **opts)
+    v, g = store.c(), graph.c()
+    return int(lib().deg_search_resident_waves(C.byref(v), C.byref(g), k, C.byref(o)))
+
+
 def search(store: VectorStore, graph: DeviceGraph, queries: torch.Tensor, seeds: torch.Tensor,
            k: int, eps: float, out=None, workspace=None, **opts):
     """RangeSearch (Algorithm 1) of every query row. Returns (ids, dists, stats)."""
@@ -503,6 +512,10 @@ def mlp_standardise(X, mean, inv_std):
 def tune_register(dtype, dim, degree, kp_bucket, hash_slots, waves_per_cu):
     _check("deg_tune_register", lib().deg_tune_register(dtype, dim, degree, kp_bucket, hash_slots,
                                                         waves_per_cu))
+
+
+def tune_clear():
+    lib().deg_tune_clear()
 
 
 def cu_count() -> int:

@@ -50,6 +50,7 @@ struct LaunchCfg {
     int64_t region;  // slots per wave
     size_t lds;
     int grid;
+    int resident;  // blocks of the kernel resident per CU at this LDS size
     size_t off_region, off_pool, off_g, ws_bytes;
 };
 
@@ -158,10 +159,13 @@ static LaunchCfg make_cfg(const deg_vectors *v, const deg_graph *g, int64_t nq, 
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void *>(c.fn), 64,
                                                      c.lds) != hipSuccess || nb < 1)
         nb = 1;
+    c.resident = nb;
     int cus = deg_device_cu_count();
     int64_t grid = (int64_t)nb * cus;
+    // (a request beyond the resident waves would only add blocks that start once the
+    // queue has drained: it is capped at residency)
     if (t && t->waves_per_cu > 0 && t->waves_per_cu < nb) grid = (int64_t)t->waves_per_cu * cus;
-    if (o && o->waves_per_cu > 0) grid = (int64_t)o->waves_per_cu * cus;
+    if (o && o->waves_per_cu > 0) grid = (int64_t)(o->waves_per_cu < nb ? o->waves_per_cu : nb) * cus;
     if (grid > nq) grid = nq;
     if (grid < 1) grid = 1;
     c.grid = (int)grid;
@@ -244,6 +248,13 @@ extern "C" size_t deg_search_workspace_bytes(const deg_vectors *v, const deg_gra
                                              int32_t k, const deg_search_opts *o) {
     if (validate_common(v, g, k, o, false) != DEG_OK || nq < 0) return 0;
     return make_cfg(v, g, nq < 1 ? 1 : nq, k, o).ws_bytes;
+}
+
+extern "C" int32_t deg_search_resident_waves(const deg_vectors *v, const deg_graph *g, int32_t k,
+                                             const deg_search_opts *o) {
+    if (validate_common(v, g, k, o, false) != DEG_OK) return 0;
+    const LaunchCfg c = make_cfg(v, g, 1, k, o);
+    return c.fn ? c.resident : 0;
 }
 
 extern "C" deg_status deg_search(const deg_vectors *v, const deg_graph *g, const float *queries,

@@ -79,6 +79,12 @@ def tune(store, graph, queries, seeds, k, eps, k_pool=0, save=True, **opts):
             except api.DegError:
                 continue
             table.append(dict(hash_slots=hs, waves_per_cu=w, ms=ms))
+    # the library caps a request at the resident waves; record the effective value
+    # (0 = all resident) so that a cached setting never claims more than ran
+    for r in table:
+        if r["waves_per_cu"] and api.resident_waves_per_cu(store, graph, k, k_pool, r["hash_slots"],
+                                                         **opts) <= r["waves_per_cu"]:
+            r["waves_per_cu"] = 0
     best = min(table, key=lambda r: r["ms"])
     bucket = kp_bucket(kp)
     api.tune_register(store.dtype, store.dim, graph.degree, bucket, best["hash_slots"],

@@ -295,6 +295,36 @@ def test_deterministic(A):
         assert (u == v).all()
 
 
+def test_tuner_keeps_results_and_records_residency(A):
+    # the tuner's knobs (LDS table size, waves per CU) never change results, and a
+    # setting it records never asks for more waves than the kernel keeps resident
+    from paper_2307_10479_amd import tune
+    x, adj = graph(1500, 24, 30)
+    q = queries_for("int", 64, 400, 24)
+    say("tuner")
+    ref = run_gpu(A, x, adj, q, [[0]] * len(q), 10, 0.1)
+    store = A.VectorStore(dev(x), "f32", oracle.L2)
+    g = A.DeviceGraph(dev(adj))
+    try:
+        best, table = tune.tune(store, g, dev(q), dev(np.zeros((len(q), 1), np.int32)), 10, 0.1,
+                                save=False, queue_cap=BIG_L)
+        for r in table:
+            res = A.resident_waves_per_cu(store, g, 10, 0, r["hash_slots"], queue_cap=BIG_L)
+            assert res >= 1
+            assert r["waves_per_cu"] == 0 or r["waves_per_cu"] < res, (r, res)
+        got = run_gpu(A, x, adj, q, [[0]] * len(q), 10, 0.1)
+        big = run_gpu(A, x, adj, q, [[0]] * len(q), 10, 0.1, waves_per_cu=64)
+    finally:
+        A.tune_clear()
+    # ids, distances, hops and evaluations agree; the flags column may differ only
+    # in the spill bit (a smaller LDS table moves the visited set to the workspace)
+    for u, v, w in zip(ref[:2], got[:2], big[:2]):
+        assert (u == v).all() and (u == w).all()
+    for st in (got[2], big[2]):
+        assert (st[:, :2] == ref[2][:, :2]).all()
+        assert ((st[:, 2] ^ ref[2][:, 2]) & ~2 == 0).all()
+
+
 def test_parity_cfg2_full_size_sampled(A):
     """1M x 128 workload in the bench's launch configuration (default options, all
     10,000 queries in one persistent launch); 300 sampled queries checked against

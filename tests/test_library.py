@@ -78,6 +78,11 @@ def test_argument_validation_rejects_before_any_gpu_call(L):
     o.trace_interval = 2
     v, g = _vec_graph(api, degree=80)
     assert call(v, g) == 2
+    # the residency query answers 0 for arguments a search would reject
+    v, g = _vec_graph(api, degree=5)
+    assert L.deg_search_resident_waves(C.byref(v), C.byref(g), 10, C.byref(o)) == 0
+    v, g = _vec_graph(api)
+    assert L.deg_search_resident_waves(C.byref(v), C.byref(g), 0, C.byref(o)) == 0
 
 
 def test_knn_and_mlp_argument_validation(L):
