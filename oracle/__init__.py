@@ -98,6 +98,13 @@ def _declare(L):
     L.or_build.restype = I32
     L.or_build.argtypes = [P, I64, I64, I64, I32, I32, I32, F32, I32, F32, I32, I32, I64, U64, P, P,
                            P, I32]
+    L.or_graph_extend_with.restype = I32
+    L.or_graph_extend_with.argtypes = [P, I64, P, P, I64, I32, F32, I32, I32]
+    L.or_build_batched.restype = I32
+    L.or_build_batched.argtypes = [P, I64, I64, I64, I32, I32, I32, F32, I32, F32, I32, I32, I64,
+                                   P, P, P]
+    L.or_build_block_size.restype = I64
+    L.or_build_block_size.argtypes = [I64, I64, I64]
     L.or_check_graph.restype = I32
     L.or_check_graph.argtypes = [P, I64, I32, P, P, I64, I64, I32, P]
     L.or_bf16_encode.restype = C.c_uint16
@@ -306,6 +313,12 @@ class Graph:
         return lib().or_graph_extend(self.h, v, k_ext, eps_ext, k_opt, eps_opt, i_opt,
                                      int(do_opt))
 
+    def extend_with(self, v, ids, dists, k_opt=30, eps_opt=0.001, i_opt=5, do_opt=True):
+        """The edits for vertex v given its search result (sorted ids and distances)."""
+        ids, dists = _i32(ids), _f32(dists)
+        return lib().or_graph_extend_with(self.h, v, _p(ids), _p(dists), len(ids), k_opt, eps_opt,
+                                          i_opt, int(do_opt))
+
     def optimize_edge(self, v1, v2, i_opt=5, k_opt=30, eps_opt=0.001):
         return lib().or_graph_optimize_edge(self.h, v1, v2, i_opt, k_opt, eps_opt)
 
@@ -350,6 +363,30 @@ def build_graph(vec, d, metric=L2, k_ext=60, eps_ext=0.2, k_opt=30, eps_opt=0.00
         raise RuntimeError("or_build failed (%d)" % rc)
     return adj, w, dict(zip(["phase2", "opt_calls", "opt_commit", "opt_revert", "case_a",
                              "case_b", "searches", "err"], cnt.tolist()))
+
+
+def build_graph_batched(vec, d, batch, metric=L2, k_ext=60, eps_ext=0.2, k_opt=30, eps_opt=0.001,
+                        i_opt=5, do_opt=True):
+    """Construction in blocks of at most `batch` vertices whose searches all run on
+    the graph as it stands when the block starts; the edits then follow in id
+    order (batch = 1 is the one-at-a-time build of Sec. 5.2). Returns adjacency,
+    weights and counters like build_graph."""
+    vec = _f32(vec)
+    n, m = vec.shape
+    adj = np.empty((n, d), np.int32)
+    w = np.empty((n, d), np.float32)
+    cnt = np.zeros(8, np.int64)
+    rc = lib().or_build_batched(_p(vec), n, m, m, metric, d, k_ext, eps_ext, k_opt, eps_opt, i_opt,
+                                int(do_opt), batch, _p(adj), _p(w), _p(cnt))
+    if rc:
+        raise RuntimeError("or_build_batched failed (%d)" % rc)
+    return adj, w, dict(zip(["phase2", "opt_calls", "opt_commit", "opt_revert", "case_a",
+                             "case_b", "searches", "err"], cnt.tolist()))
+
+
+def build_block_size(nv, batch, left) -> int:
+    """Vertices in the next block of the batched build."""
+    return int(lib().or_build_block_size(nv, batch, left))
 
 
 def check_graph(adj, vec=None, w=None, metric=L2):

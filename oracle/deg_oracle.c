@@ -11,7 +11,8 @@
  *   or_knn64             -- Eq. (knn) in FP64, brute force
  *   graph construction   -- Sec. 5.2 steps 1-6, Algorithm 2 (checkMRNG),
  *                           Algorithm 3 (ExtendGraph), Algorithm 4 (optimizeEdge),
- *                           Algorithm 5 (dynamicEdgeOptimization)
+ *                           Algorithm 5 (dynamicEdgeOptimization); a batched
+ *                           schedule (searches of a block on one snapshot)
  *   or_check_graph       -- Sec. 5.1 even regularity, undirected, no loops,
  *                           connectivity and 2-edge-connectivity (no bridges)
  *   encodings            -- BF16 round-to-nearest-even, OCP FP8 e4m3 with a row scale
@@ -1289,13 +1290,37 @@ int or_graph_optimize_edge(Graph *g, int32_t v1, int32_t v2, int32_t i_opt, int3
  * Then optionally optimizeEdge for the new edges whose far end was not in the
  * search result. Returns 0 on success.
  */
+static int extend_apply(Graph *g, int64_t v, const Ent *S, int64_t ns, int32_t k_opt,
+                        float eps_opt, int32_t i_opt, int32_t do_opt);
+
 int or_graph_extend(Graph *g, int64_t v, int32_t k_ext, float eps_ext, int32_t k_opt,
                     float eps_opt, int32_t i_opt, int32_t do_opt) {
-    int32_t d = g->d;
     if (v != g->nv) return -1;
     Ent *S = (Ent *)malloc(sizeof(Ent) * ((size_t)k_ext + 1));
     int32_t seed = 0;
     int64_t ns = graph_search(g, &seed, 1, v, k_ext, eps_ext, S);
+    int rc = extend_apply(g, v, S, ns, k_opt, eps_opt, i_opt, do_opt);
+    free(S);
+    return rc;
+}
+
+/* The edits for vertex v (== nv) given a search result computed elsewhere
+ * (ids and distances sorted by (distance, id)). */
+int or_graph_extend_with(Graph *g, int64_t v, const int32_t *ids, const float *dists, int64_t ns,
+                         int32_t k_opt, float eps_opt, int32_t i_opt, int32_t do_opt) {
+    Ent *S = (Ent *)malloc(sizeof(Ent) * ((size_t)ns + 1));
+    for (int64_t i = 0; i < ns; ++i) S[i] = (Ent){dists[i], ids[i]};
+    int rc = extend_apply(g, v, S, ns, k_opt, eps_opt, i_opt, do_opt);
+    free(S);
+    return rc;
+}
+
+/* The edits of Sec. 5.2 steps 3-6 for vertex v (== nv), given the result S of
+ * its search (sorted by (distance, id)). */
+static int extend_apply(Graph *g, int64_t v, const Ent *S, int64_t ns, int32_t k_opt,
+                        float eps_opt, int32_t i_opt, int32_t do_opt) {
+    int32_t d = g->d;
+    if (v != g->nv) return -1;
     int32_t U[512];
     float Ud[512];
     int nu = 0;
@@ -1333,7 +1358,6 @@ int or_graph_extend(Graph *g, int64_t v, int32_t k_ext, float eps_ext, int32_t k
         }
     }
     if (nu < d) {
-        free(S);
         g->err = 10;
         return -2;
     }
@@ -1358,7 +1382,6 @@ int or_graph_extend(Graph *g, int64_t v, int32_t k_ext, float eps_ext, int32_t k
             if (has_edge(g, (int32_t)v, cand[i].id))
                 or_graph_optimize_edge(g, (int32_t)v, cand[i].id, i_opt, k_opt, eps_opt);
     }
-    free(S);
     return g->err ? -3 : 0;
 }
 
@@ -1461,6 +1484,62 @@ int or_build(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t metric,
     if (out_counters) or_graph_counters(g, out_counters);
     or_graph_free(g);
     return 0;
+}
+
+/*
+ * Batched construction: the paper adds one vertex at a time (Sec. 5.2), each
+ * search seeing every earlier edit. Here vertices are added in blocks: the
+ * searches of a block all run on the graph as it stands when the block starts
+ * (its earlier vertices are not yet in it), then the block's vertices take
+ * their edits (steps 3-6 and, with do_opt, optimizeEdge with its own searches
+ * on the live graph) one by one in id order. A block holds at most `batch`
+ * vertices and at most an eighth of the vertices already in the graph (at
+ * least one), so early blocks stay small. batch = 1 is the one-at-a-time
+ * build. This schedule is the framework's reading, not the paper's.
+ */
+int64_t or_build_block_size(int64_t nv, int64_t batch, int64_t left) {
+    int64_t b = nv / 8;
+    if (b < 1) b = 1;
+    if (b > batch) b = batch;
+    if (b > left) b = left;
+    return b;
+}
+
+int or_build_batched(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t metric,
+                     int32_t d, int32_t k_ext, float eps_ext, int32_t k_opt, float eps_opt,
+                     int32_t i_opt, int32_t do_opt, int64_t batch, int32_t *out_adj,
+                     float *out_w, int64_t *out_counters) {
+    if (batch < 1 || k_ext < 1) return -1;
+    Graph *g = or_graph_create(vec, n, m, vs, metric, d);
+    if (!g) return -1;
+    if (or_graph_init(g)) {
+        or_graph_free(g);
+        return -2;
+    }
+    const int64_t stride = (int64_t)k_ext + 1;
+    const int64_t cap = batch < n ? batch : n;
+    Ent *res = (Ent *)malloc(sizeof(Ent) * (size_t)(stride * cap));
+    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    int rc = 0;
+    for (int64_t s = d + 1; s < n && rc == 0;) {
+        const int64_t bsz = or_build_block_size(g->nv, batch, n - s);
+        for (int64_t i = 0; i < bsz; ++i) {
+            int32_t seed = 0;
+            cnt[i] = graph_search(g, &seed, 1, s + i, k_ext, eps_ext, res + i * stride);
+        }
+        for (int64_t i = 0; i < bsz && rc == 0; ++i)
+            if (extend_apply(g, s + i, res + i * stride, cnt[i], k_opt, eps_opt, i_opt, do_opt))
+                rc = -3;
+        s += bsz;
+    }
+    free(res);
+    free(cnt);
+    if (rc == 0) {
+        or_graph_export(g, out_adj, out_w, NULL);
+        if (out_counters) or_graph_counters(g, out_counters);
+    }
+    or_graph_free(g);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -181,3 +181,62 @@ def test_checker_finds_a_bridge():
         adj[5 + i, :len(r2)] = r2
     chk = oracle.check_graph(adj)
     assert chk["flags"] == 0 and chk["bridges"] == 0
+
+
+# ---------------------------------------------------------------- batched schedule
+def test_block_size_schedule():
+    # at most `batch`, at most an eighth of the graph (at least one), never past the end
+    assert oracle.build_block_size(31, 64, 10_000) == 3
+    assert oracle.build_block_size(7, 64, 10_000) == 1
+    assert oracle.build_block_size(10_000, 64, 10_000) == 64
+    assert oracle.build_block_size(10_000, 4096, 10_000) == 1250
+    assert oracle.build_block_size(10_000, 4096, 5) == 5
+    assert oracle.build_block_size(10_000, 1, 5) == 1
+
+
+@pytest.mark.parametrize("do_opt", [False, True])
+def test_batched_build_of_one_is_the_sequential_build(do_opt):
+    x = synth.small_int(21, 700, 16, hi=64)
+    a1, w1, c1 = oracle.build_graph(x, 10, k_ext=20, eps_ext=0.2, k_opt=10, do_opt=do_opt)
+    a2, w2, c2 = oracle.build_graph_batched(x, 10, 1, k_ext=20, eps_ext=0.2, k_opt=10, do_opt=do_opt)
+    assert (a1 == a2).all() and (w1 == w2).all()
+    assert c1 == c2
+
+
+def _batched_by_hand(x, d, batch, k_ext, eps_ext, do_opt, metric=oracle.L2):
+    # the block schedule driven from outside: each block's searches run through the
+    # public RangeSearch on the adjacency exported when the block starts, then the
+    # edits go in id order
+    g = oracle.Graph(x, d, metric)
+    g.init()
+    n = len(x)
+    s = d + 1
+    while s < n:
+        b = oracle.build_block_size(g.nv, batch, n - s)
+        adj, _, _ = g.export()
+        ids, ds, _ = oracle.range_search(x, adj, x[s:s + b], [0], k_ext, eps_ext, metric)
+        for i in range(b):
+            live = ids[i] >= 0
+            assert g.extend_with(s + i, ids[i][live], ds[i][live], k_opt=d, do_opt=do_opt) == 0
+        s += b
+    adj, w, _ = g.export()
+    return adj, w
+
+
+@pytest.mark.parametrize("batch,do_opt,metric", [(16, False, oracle.L2), (64, True, oracle.L2),
+                                                 (1000, False, oracle.IP)])
+def test_batched_build_matches_the_schedule_and_keeps_invariants(batch, do_opt, metric):
+    n, d = 900, 10
+    x = synth.small_int(22, n, 16, hi=64) if metric == oracle.L2 else synth.small_unit(22, n, 16)
+    adj, w, cnt = oracle.build_graph_batched(x, d, batch, metric, k_ext=2 * d, eps_ext=0.2,
+                                             k_opt=d, do_opt=do_opt)
+    chk = oracle.check_graph(adj, x, w, metric)
+    assert chk["flags"] == 0, chk
+    assert chk["edges"] == n * d // 2 and chk["bridges"] == 0
+    assert cnt["err"] == 0
+    a2, w2 = _batched_by_hand(x, d, batch, 2 * d, 0.2, do_opt, metric)
+    assert (adj == a2).all() and (w == w2).all()
+    # a block's searches do not see each other: with a large batch the graph differs
+    # from the one-at-a-time build
+    a1, _, _ = oracle.build_graph(x, d, metric, k_ext=2 * d, eps_ext=0.2, k_opt=d, do_opt=do_opt)
+    assert (a1 != adj).any()
