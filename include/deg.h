@@ -281,6 +281,52 @@ size_t deg_medoid_workspace_bytes(int64_t n, int32_t dim);
 deg_status deg_medoid(const float *vec, int64_t n, int32_t dim, int64_t stride, int32_t metric,
                       int32_t *out_id, void *workspace, size_t ws_bytes, void *stream);
 
+/*
+ * Graph construction (Sec. 5.2 with Algorithm 3's scheme C: the complete graph
+ * on vertices 0..d, then every further vertex in id order: a search for its
+ * k_ext nearest vertices from vertex 0, a pass over the result that takes each
+ * vertex b passing the MRNG check (Algorithm 2) against the tentative
+ * neighbours, cuts b's longest edge to a vertex outside them (equal weights:
+ * the smaller id) and gives the new vertex both ends, and a second pass
+ * without the check while fewer than d were found). optimizeEdge (Algorithm
+ * 4) is not applied.
+ * Batched schedule: the searches of a block of vertices all run on the graph
+ * as it stands when the block starts, in one deg_search launch (FP32 traversal,
+ * default options); the block's edits then follow in id order on the host,
+ * each on the live graph, and the changed rows are copied to `adjacency`
+ * before the next block. A block holds at most `batch` vertices and at most
+ * nv / 8 of the nv vertices already in the graph (at least 1); batch = 1 is
+ * the one-at-a-time build.
+ *   v              the n vectors (device, DEG_F32, L2 or IP): the searched store,
+ *                  whose rows are also the new vertices' queries
+ *   host_vectors   the same vectors on the host (row stride host_stride floats),
+ *                  for the distances of the edges the edits create (FP32, the
+ *                  library's fixed reduction order, equal to the search's)
+ *   adjacency      device, n x degree int32, overwritten: the built graph,
+ *                  every row holding exactly `degree` neighbours
+ *   weights        nullable host n x degree FP32: the edge weights, row-aligned
+ *   counters       nullable host int64[4]: {blocks, searches, vertices that
+ *                  needed the pass without MRNG check, searches that lost a
+ *                  candidate to the capacity of S (0 means every search was
+ *                  Algorithm 1's exactly)}
+ * degree even in [4, 128], n >= degree + 1, k_ext in [1, 1024], eps_ext >= 0,
+ * batch >= 1. The call allocates its own device and pinned host buffers,
+ * frees them before it returns, and returns when the graph is complete on
+ * `stream` (it synchronises the stream once per block). DEG_ERR_UNSUPPORTED
+ * when a search result cannot supply degree neighbours (k_ext too small).
+ */
+typedef struct {
+    int32_t degree;  /* d */
+    int32_t k_ext;   /* result size of a new vertex's search */
+    float eps_ext;   /* range factor of that search */
+    int32_t reserved;
+    int64_t batch;   /* the most vertices in one block */
+} deg_build_params;
+
+deg_status deg_build_graph(const deg_vectors *v, const float *host_vectors, int64_t host_stride,
+                           const deg_build_params *p, int32_t *adjacency, float *weights,
+                           int64_t *counters, void *stream);
+
 /* Reduced-precision stores. BF16: round to nearest even. FP8: per row
  * scale = max|x| / 448 (1 if the row is zero), code = E4M3 round to nearest
  * even of x / scale, saturating at 448. Rows beyond dim are zero-filled up to

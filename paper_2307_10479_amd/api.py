@@ -69,10 +69,15 @@ class DegQueryDesc(C.Structure):
                 ("k", C.c_int32), ("eps", C.c_float), ("out_offset", C.c_int64)]
 
 
+class DegBuildParams(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("k_ext", C.c_int32), ("eps_ext", C.c_float),
+                ("reserved", C.c_int32), ("batch", C.c_int64)]
+
+
 EXPORTS = [
     "deg_search_workspace_bytes", "deg_search_resident_waves", "deg_search", "deg_search_noalloc",
     "deg_search_indexed",
-    "deg_search_batch",
+    "deg_search_batch", "deg_build_graph",
     "deg_knn_workspace_bytes", "deg_knn_bruteforce", "deg_medoid_workspace_bytes", "deg_medoid",
     "deg_encode_bf16", "deg_encode_fp8", "deg_mlp_workspace_bytes", "deg_mlp_train_step",
     "deg_mlp_forward", "deg_mlp_forward_bf16", "deg_mlp_export_bf16", "deg_mlp_feature_stats",
@@ -97,6 +102,7 @@ def load_library(path: Path | None = None):
     sigs = {
         "deg_search_workspace_bytes": (SZ, [pv, pg, I64, I32, po]),
         "deg_search_resident_waves": (I32, [pv, pg, I32, po]),
+        "deg_build_graph": (I32, [pv, P, I64, C.POINTER(DegBuildParams), P, P, P, V]),
         "deg_search": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, P, SZ, V]),
         "deg_search_noalloc": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, V]),
         "deg_search_indexed": (I32, [pv, pg, P, I64, I32, F, po, P, P, P, P, SZ, V]),
@@ -461,6 +467,31 @@ def medoid(base: torch.Tensor, metric: int = L2) -> int:
     _check("deg_medoid", L.deg_medoid(_ptr(base), n, m, base.stride(0), metric, _ptr(out),
                                       _ptr(ws), ws.numel(), _stream()))
     return int(out.item())
+
+
+# ------------------------------------------------------------------ construction
+def build_graph(store: VectorStore, host_base, degree, k_ext, eps_ext, batch=4096):
+    """Graph construction (Sec. 5.2, Algorithm 3 without optimizeEdge) with the
+    searches of each block of new vertices batched on the GPU.
+
+    store: the FP32 VectorStore of all n vectors; host_base: the same (n, dim)
+    float32 array on the host. Returns (adjacency (n, degree) int32 on the device,
+    weights (n, degree) float32 numpy, counters dict)."""
+    import numpy as np
+    hb = np.ascontiguousarray(host_base, dtype=np.float32)
+    n = store.n
+    if hb.shape[0] != n or hb.shape[1] != store.dim:
+        raise ValueError("host_base must be the store's %d x %d vectors" % (n, store.dim))
+    adj = torch.empty((n, degree), dtype=torch.int32, device="cuda")
+    w = np.empty((n, degree), np.float32)
+    cnt = np.zeros(4, np.int64)
+    p = DegBuildParams(degree=int(degree), k_ext=int(k_ext), eps_ext=float(eps_ext), reserved=0,
+                       batch=int(batch))
+    v = store.c()
+    _check("deg_build_graph", lib().deg_build_graph(
+        C.byref(v), C.c_void_p(hb.ctypes.data), hb.shape[1], C.byref(p), _ptr(adj),
+        C.c_void_p(w.ctypes.data), C.c_void_p(cnt.ctypes.data), _stream()))
+    return adj, w, dict(zip(["blocks", "searches", "phase2", "lossy"], cnt.tolist()))
 
 
 # ------------------------------------------------------------------ MLP

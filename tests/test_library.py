@@ -85,6 +85,22 @@ def test_argument_validation_rejects_before_any_gpu_call(L):
     assert L.deg_search_resident_waves(C.byref(v), C.byref(g), 0, C.byref(o)) == 0
 
 
+def test_build_argument_validation(L):
+    from paper_2307_10479_amd import api
+    P = C.c_void_p(0x400000)
+
+    def call(degree=10, k_ext=20, eps=0.2, batch=64, dtype=0, n=100, dim=16, stride=16, hstride=16):
+        v = api.DegVectors()
+        v.data, v.n, v.dim, v.row_stride, v.dtype, v.metric = P, n, dim, stride, dtype, 0
+        p = api.DegBuildParams(degree=degree, k_ext=k_ext, eps_ext=eps, reserved=0, batch=batch)
+        return L.deg_build_graph(C.byref(v), P, hstride, C.byref(p), P, None, None, None)
+
+    bad = [call(degree=5), call(degree=2), call(degree=130), call(k_ext=0), call(k_ext=2000),
+           call(eps=-1.0), call(eps=float("nan")), call(batch=0), call(dtype=1), call(n=10),
+           call(hstride=8)]
+    assert all(b == 1 for b in bad), bad
+
+
 def test_knn_and_mlp_argument_validation(L):
     P = C.c_void_p(0x400000)
     assert L.deg_knn_bruteforce(P, 100, 16, 15, P, 10, 16, 10, 0, None, P, P, P, 1 << 20, None) == 1
