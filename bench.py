@@ -332,6 +332,100 @@ def run_degree_sweep(a):
     return 0
 
 
+def run_build(a):
+    """Graph construction throughput (Sec. 5.2 / Algorithm 3 scheme C, no optimizeEdge)
+    on the 1M x 128 workload, degree 30, k_ext 60, eps_ext 0.2: the searches of each
+    block of new vertices run as one persistent launch, the edits on the host in id
+    order. Quality: QPS at recall@10 >= target of the FP32 search on the built graph
+    next to the stored graph (one vertex at a time with optimizeEdge)."""
+    import time
+
+    import torch
+
+    import synth
+    from paper_2307_10479_amd import api, metrics
+    from synth.io import load_graph
+    api.lib()
+    torch.cuda.set_device(0)
+    base, q = synth.cfg2()
+    n = a.build_n or base.shape[0]
+    base = np.ascontiguousarray(base[:n])
+    d, k_ext, eps_ext = 30, 60, 0.2
+    dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    xb, Q = dev(base), dev(q)
+    store = api.VectorStore(xb, "f32", api.L2)
+    builds = {}
+    for batch in a.build_batch:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        adj, w, cnt = api.build_graph(store, base, d, k_ext, eps_ext, batch)
+        torch.cuda.synchronize()
+        sec = time.perf_counter() - t0
+        builds[batch] = (adj, dict(cnt, seconds=round(sec, 3), vertices_per_s=round(n / sec, 1)))
+        log("build n %d batch %d: %.2f s (%.0f vertices/s) blocks %d search %.2f s edits %.2f s "
+            "lossy %d" % (n, batch, sec, n / sec, cnt["blocks"], cnt["search_us"] / 1e6,
+                          cnt["edit_us"] / 1e6, cnt["lossy"]))
+    # search quality of the built graphs against the stored one-at-a-time graph
+    nq, k = q.shape[0], 10
+    sweeps = {}
+    gt = None
+    stored = ROOT / "data" / "cfg2.deg"
+    graphs = {("built_b%d" % b): g for b, (g, _) in builds.items()}
+    if n == 1_000_000 and stored.exists():
+        meta = json.loads((ROOT / "data" / "cfg2.meta.json").read_text())
+        gt = np.load(ROOT / "data" / "cfg2.gt.npz")["ids"]
+        graphs["stored_sequential_opt"] = dev(load_graph(stored)[0])
+        seed = int(meta["medoid"])
+    else:
+        gt_ids, _ = api.knn_bruteforce(xb, Q, k, api.L2)
+        gt = gt_ids.cpu().numpy()
+        seed = api.medoid(xb, api.L2)
+        meta = {}
+    seeds = torch.full((nq, 1), seed, dtype=torch.int32, device="cuda")
+    for name, g in graphs.items():
+        G = api.DeviceGraph(g)
+        rows = []
+        for eps in (0.0, 0.04, 0.08, 0.1, 0.12, 0.14, 0.16, 0.18, 0.2, 0.22, 0.25, 0.3):
+            times, (ids, ds, st) = _timed_runs(
+                torch, lambda e=eps: api.search(store, G, Q, seeds, k, e), 1, 3)
+            ms = float(np.median(times))
+            r = metrics.recall_at_k(ids.cpu().numpy(), gt, k)
+            rows.append(dict(eps=eps, recall_at_10=round(r, 5), ms=round(ms, 3),
+                             qps=round(nq / (ms / 1e3), 1)))
+            log("graph %s eps %.2f recall@10 %.4f %.3f ms %.0f QPS" % (name, eps, r, ms,
+                                                                       nq / (ms / 1e3)))
+            if r >= a.recall:
+                break
+        sweeps[name] = rows
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle
+        ns = 12_000
+        t0 = time.perf_counter()
+        oracle.build_graph_batched(base[:ns], d, a.build_batch[0], oracle.L2, k_ext=k_ext,
+                                   eps_ext=eps_ext, do_opt=False)
+        sec = time.perf_counter() - t0
+        cpu = dict(value=round(ns / sec, 1), unit="vertices/s", cores=1, kind="oracle",
+                   sample="batched build of the first %d vertices (block limit %d, no "
+                          "optimizeEdge), %.1f s" % (ns, a.build_batch[0], sec))
+    head_b = a.build_batch[0]
+    head = builds[head_b][1]
+    out = {
+        "metric": "graph construction throughput (vertices/s)", "value": head["vertices_per_s"],
+        "unit": "vertices/s", "n_gpus": 1, "steps": 1, "warmup": 0,
+        "ms_per_step": round(head["seconds"] * 1e3, 1), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "DEG construction, %d x 128 integer vectors, d=30, k_ext=60, "
+                               "eps_ext=0.2, block limit %d" % (n, head_b),
+                   "builds": {str(b): c for b, (_, c) in builds.items()},
+                   "stored_graph_build_seconds": meta.get("build_seconds"),
+                   "search_quality": sweeps},
+        "roofline": None, "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def run_explore(a):
     """Exploration at k = 1000 on the 1,183,514 x 100 inner-product workload (the
     protocol of the paper's exploration experiment: 10,000 base vertices, each its
@@ -699,6 +793,11 @@ def main(argv=None):
                     help="exploration at k = 1000 (cfg3), with and without shown vertices excluded")
     ap.add_argument("--degree-sweep", action="store_true",
                     help="QPS at recall against the graph degree (30, 64, 80) on a 30,000-vector subset")
+    ap.add_argument("--build", action="store_true",
+                    help="time graph construction with block-batched searches (1M x 128, d=30)")
+    ap.add_argument("--build-n", type=int, default=0, help="construction: first N vectors only")
+    ap.add_argument("--build-batch", type=lambda s: [int(x) for x in s.split(",")],
+                    default=[16384], help="construction: block limits (comma list)")
     ap.add_argument("--knn", action="store_true",
                     help="time the brute-force ground truth (matrix cores) instead of the search")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -709,6 +808,8 @@ def main(argv=None):
               "and splitting the queries, but only --gpus 1 is measured here", file=sys.stderr)
         return 2
 
+    if a.build:
+        return run_build(a)
     if a.knn:
         return run_knn(a)
     if a.explore:

@@ -305,15 +305,18 @@ deg_status deg_medoid(const float *vec, int64_t n, int32_t dim, int64_t stride, 
  *   adjacency      device, n x degree int32, overwritten: the built graph,
  *                  every row holding exactly `degree` neighbours
  *   weights        nullable host n x degree FP32: the edge weights, row-aligned
- *   counters       nullable host int64[4]: {blocks, searches, vertices that
+ *   counters       nullable host int64[6]: {blocks, searches, vertices that
  *                  needed the pass without MRNG check, searches that lost a
  *                  candidate to the capacity of S (0 means every search was
- *                  Algorithm 1's exactly)}
+ *                  Algorithm 1's exactly), microseconds from each block's row
+ *                  upload to its results on the host, microseconds of the
+ *                  host edits}
  * degree even in [4, 128], n >= degree + 1, k_ext in [1, 1024], eps_ext >= 0,
  * batch >= 1. The call allocates its own device and pinned host buffers,
  * frees them before it returns, and returns when the graph is complete on
  * `stream` (it synchronises the stream once per block). DEG_ERR_UNSUPPORTED
- * when a search result cannot supply degree neighbours (k_ext too small).
+ * when a search result cannot supply degree neighbours (k_ext too small);
+ * DEG_ERR_HIP when an allocation (device or host) or a HIP call fails.
  */
 typedef struct {
     int32_t degree;  /* d */

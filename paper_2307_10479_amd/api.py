@@ -484,14 +484,15 @@ def build_graph(store: VectorStore, host_base, degree, k_ext, eps_ext, batch=409
         raise ValueError("host_base must be the store's %d x %d vectors" % (n, store.dim))
     adj = torch.empty((n, degree), dtype=torch.int32, device="cuda")
     w = np.empty((n, degree), np.float32)
-    cnt = np.zeros(4, np.int64)
+    cnt = np.zeros(6, np.int64)
     p = DegBuildParams(degree=int(degree), k_ext=int(k_ext), eps_ext=float(eps_ext), reserved=0,
                        batch=int(batch))
     v = store.c()
     _check("deg_build_graph", lib().deg_build_graph(
         C.byref(v), C.c_void_p(hb.ctypes.data), hb.shape[1], C.byref(p), _ptr(adj),
         C.c_void_p(w.ctypes.data), C.c_void_p(cnt.ctypes.data), _stream()))
-    return adj, w, dict(zip(["blocks", "searches", "phase2", "lossy"], cnt.tolist()))
+    return adj, w, dict(zip(["blocks", "searches", "phase2", "lossy", "search_us", "edit_us"],
+                            cnt.tolist()))
 
 
 # ------------------------------------------------------------------ MLP

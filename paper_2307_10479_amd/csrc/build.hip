@@ -20,8 +20,10 @@
 
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <vector>
 
 #include "deg.h"
@@ -48,43 +50,68 @@ float dist_c32x4(const float *x, const float *q, int m, int metric) {
     return metric == DEG_METRIC_L2 ? p[0] : 1.0f - p[0];
 }
 
-// Host copy of the growing graph: rows of up to d (neighbour, weight) pairs,
-// filled from the front; removal keeps the order of the remaining entries.
+// Host copy of the growing graph. A vertex owns one 64-byte aligned record: a
+// header (neighbour count, block of the last change) and up to d (neighbour,
+// weight) slots filled from the front, so one fetch brings everything an edit
+// reads; removal keeps the order of the remaining entries.
+union Cell {
+    struct {
+        int32_t id;
+        float w;
+    } e;
+    struct {
+        int32_t cnt;
+        int32_t stamp;
+    } h;
+};
+
 struct HostGraph {
     int64_t n;
     int d;
-    std::vector<int32_t> nbr;
-    std::vector<float> w;
-    std::vector<int32_t> cnt;
-    std::vector<int64_t> stamp;  // block in which the row last changed
-    std::vector<int32_t> dirty;  // rows changed since the last upload
-    int64_t block = 0;
+    int64_t stride;  // cells per record, a multiple of 8 (64 bytes)
+    Cell *cells = nullptr;
+    std::vector<int32_t> dirty;  // records changed since the last upload
+    int32_t block = 0;
     bool broken = false;
 
-    HostGraph(int64_t n_, int d_)
-        : n(n_), d(d_), nbr((size_t)n_ * d_, -1), w((size_t)n_ * d_, 0.0f), cnt(n_, 0),
-          stamp(n_, -1) {}
+    HostGraph(int64_t n_, int d_) : n(n_), d(d_), stride(((int64_t)d_ + 1 + 7) / 8 * 8) {
+        cells = static_cast<Cell *>(aligned_alloc(64, sizeof(Cell) * (size_t)(n * stride)));
+        if (!cells) return;
+        for (int64_t a = 0; a < n; ++a) {
+            Cell *c = cells + a * stride;
+            c[0].h.cnt = 0;
+            c[0].h.stamp = -1;
+            for (int j = 1; j <= d; ++j) c[j].e = {-1, 0.0f};
+        }
+    }
+    ~HostGraph() { free(cells); }
+    HostGraph(const HostGraph &) = delete;
+    HostGraph &operator=(const HostGraph &) = delete;
 
+    Cell *rec(int32_t a) { return cells + (int64_t)a * stride; }
+    int32_t &cnt(int32_t a) { return rec(a)[0].h.cnt; }
+    Cell *r(int32_t a) { return rec(a) + 1; }
     void touch(int32_t a) {
-        if (stamp[a] != block) {
-            stamp[a] = block;
+        int32_t &st = rec(a)[0].h.stamp;
+        if (st != block) {
+            st = block;
             dirty.push_back(a);
         }
     }
-    int find(int32_t a, int32_t b) const {
-        const int32_t *r = &nbr[(size_t)a * d];
-        for (int j = 0; j < cnt[a]; ++j)
-            if (r[j] == b) return j;
+    int find(int32_t a, int32_t b) {
+        const Cell *x = r(a);
+        const int c = cnt(a);
+        for (int j = 0; j < c; ++j)
+            if (x[j].e.id == b) return j;
         return -1;
     }
     void half_add(int32_t a, int32_t b, float wt) {
-        if (cnt[a] >= d) {
+        int32_t &c = cnt(a);
+        if (c >= d) {
             broken = true;
             return;
         }
-        nbr[(size_t)a * d + cnt[a]] = b;
-        w[(size_t)a * d + cnt[a]] = wt;
-        ++cnt[a];
+        r(a)[c++].e = {b, wt};
         touch(a);
     }
     void half_remove(int32_t a, int32_t b) {
@@ -93,15 +120,10 @@ struct HostGraph {
             broken = true;
             return;
         }
-        int32_t *r = &nbr[(size_t)a * d];
-        float *ww = &w[(size_t)a * d];
-        for (; j + 1 < cnt[a]; ++j) {
-            r[j] = r[j + 1];
-            ww[j] = ww[j + 1];
-        }
-        --cnt[a];
-        r[cnt[a]] = -1;
-        ww[cnt[a]] = 0.0f;
+        Cell *x = r(a);
+        int32_t &c = cnt(a);
+        for (; j + 1 < c; ++j) x[j] = x[j + 1];
+        x[--c].e = {-1, 0.0f};
         touch(a);
     }
     void add_edge(int32_t a, int32_t b, float wt) {
@@ -124,57 +146,89 @@ struct HostGraph {
 bool extend_vertex(HostGraph &G, const float *vec, int64_t vs, int m, int metric, int32_t v,
                    const int32_t *ids, const float *ds, int ns, int64_t &phase2) {
     const int d = G.d;
-    std::vector<int32_t> U;
-    std::vector<float> Ud;
-    U.reserve(d);
-    Ud.reserve(d);
-    auto in_u = [&](int32_t x) {
-        for (int32_t u : U)
-            if (u == x) return true;
-        return false;
+    int32_t U[128];
+    float Ud[128];
+    bool pend[128];  // U[t] is a cut edge's far end whose distance is not computed yet
+    int nu = 0;
+    // the candidates' records are read in turn below: start their fetches now
+    for (int i = 0; i < ns; ++i) {
+        const char *a = reinterpret_cast<const char *>(G.rec(ids[i]));
+        for (size_t o = 0; o < sizeof(Cell) * (size_t)(d + 1); o += 64) __builtin_prefetch(a + o);
+    }
+    // membership in U: a 256-bit filter of hashed ids answers most lookups, the
+    // short list the rest
+    uint64_t filt[4] = {0, 0, 0, 0};
+    auto hbit = [](int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> 24; };
+    auto in_u = [&](int32_t x) -> int {
+        const uint32_t h = hbit(x);
+        if (!((filt[h >> 6] >> (h & 63)) & 1)) return -1;
+        for (int t = 0; t < nu; ++t)
+            if (U[t] == x) return t;
+        return -1;
     };
-    for (int pass = 0; pass < 2 && (int)U.size() < d; ++pass) {
+    auto push = [&](int32_t x, float dx, bool later) {
+        const uint32_t h = hbit(x);
+        filt[h >> 6] |= 1ull << (h & 63);
+        U[nu] = x;
+        Ud[nu] = dx;
+        pend[nu++] = later;
+    };
+    auto dist_of = [&](int t) {
+        if (pend[t]) {
+            Ud[t] = dist_c32x4(vec + (size_t)U[t] * vs, vec + (size_t)v * vs, m, metric);
+            pend[t] = false;
+        }
+        return Ud[t];
+    };
+    for (int pass = 0; pass < 2 && nu < d; ++pass) {
         if (pass == 1) ++phase2;
-        for (int i = 0; i < ns && (int)U.size() < d; ++i) {
+        for (int i = 0; i < ns && nu < d; ++i) {
             const int32_t b = ids[i];
             const float db = ds[i];
-            if (in_u(b)) continue;
-            if (pass == 0) {
-                // MRNG check of (v, b) against the tentative neighbours u of v
-                // that are also neighbours of b: the edge is kept out when it is
-                // longer than both other sides of such a triangle
-                bool ok = true;
-                for (size_t t = 0; t < U.size() && ok; ++t) {
-                    const int j = G.find(b, U[t]);
-                    if (j < 0) continue;
-                    const float wbu = G.w[(size_t)b * d + j];
-                    const float mx = Ud[t] > wbu ? Ud[t] : wbu;
-                    if (db > mx) ok = false;
-                }
-                if (!ok) continue;
-            }
-            // b's longest edge to a vertex outside U (equal weights: smaller id)
+            if (in_u(b) >= 0) continue;
+            // one pass over b's row: the MRNG check of (v, b) against the
+            // tentative neighbours u of v adjacent to b (the edge stays out when
+            // it is longer than both other sides of such a triangle), and b's
+            // longest edge to a vertex outside U (equal weights: smaller id)
+            const Cell *x = G.r(b);
+            const int cb = G.cnt(b);
+            bool ok = true;
             int32_t far = -1;
             float fw = -INFINITY;
-            for (int j = 0; j < G.cnt[b]; ++j) {
-                const int32_t c = G.nbr[(size_t)b * d + j];
-                if (in_u(c)) continue;
-                const float wt = G.w[(size_t)b * d + j];
-                if (wt > fw || (wt == fw && c < far)) {
+            for (int j = 0; j < cb; ++j) {
+                const int32_t c = x[j].e.id;
+                const float wt = x[j].e.w;
+                const int t = in_u(c);
+                if (t >= 0) {
+                    if (pass == 0) {
+                        const float du = dist_of(t);
+                        if (db > (du > wt ? du : wt)) ok = false;
+                    }
+                } else if (wt > fw || (wt == fw && c < far)) {
                     fw = wt;
                     far = c;
                 }
             }
-            if (far < 0) continue;
-            G.remove_edge(b, far);
-            U.push_back(b);
-            Ud.push_back(db);
-            U.push_back(far);
-            Ud.push_back(dist_c32x4(vec + (size_t)far * vs, vec + (size_t)v * vs, m, metric));
+            if ((pass == 0 && !ok) || far < 0) continue;
+            // the far end's record and vector are needed only at the end (nothing
+            // in between reads its row: it is in U from here on)
+            const char *fr = reinterpret_cast<const char *>(G.rec(far));
+            for (size_t o = 0; o < sizeof(Cell) * (size_t)(d + 1); o += 64) __builtin_prefetch(fr + o);
+            const char *fv = reinterpret_cast<const char *>(vec + (size_t)far * vs);
+            for (int o = 0; o < m * 4; o += 64) __builtin_prefetch(fv + o);
+            G.half_remove(b, far);
+            push(b, db, false);
+            push(far, 0.0f, true);
         }
     }
-    if ((int)U.size() < d) return false;
-    for (size_t j = 0; j < U.size(); ++j) G.add_edge(v, U[j], Ud[j]);
+    if (nu < d) {
+        // (the build stops here; the cut edges are completed so that no row
+        // holds half an edge)
+        for (int t = 1; t < nu; t += 2) G.half_remove(U[t], U[t - 1]);
+        return false;
+    }
+    for (int t = 1; t < nu; t += 2) G.half_remove(U[t], U[t - 1]);
+    for (int j = 0; j < nu; ++j) G.add_edge(v, U[j], dist_of(j));
     return !G.broken;
 }
 
@@ -234,6 +288,7 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
     HostGraph G(n, d);
+    if (!G.cells) return DEG_ERR_HIP;
     // the smallest DEG: the complete graph on vertices 0..d
     for (int32_t a = 0; a <= d; ++a)
         for (int32_t b = a + 1; b <= d; ++b)
@@ -290,7 +345,8 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
         if (nr == 0) return DEG_OK;
         if (nr > up_cap) return DEG_ERR_HIP;
         for (int64_t r = 0; r < nr; ++r) {
-            memcpy(h_up + r * d, &G.nbr[(size_t)G.dirty[r] * d], sizeof(int32_t) * d);
+            const Cell *x = G.r(G.dirty[r]);
+            for (int j = 0; j < d; ++j) h_up[r * d + j] = x[j].e.id;
             h_up[up_cap * d + r] = G.dirty[r];
         }
         if (hipMemcpyAsync(d_rows, h_up, sizeof(int32_t) * nr * d, hipMemcpyHostToDevice, st) !=
@@ -307,11 +363,14 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     };
 
     int64_t blocks = 0, searches = 0, phase2 = 0, lossy = 0;
+    using clk = std::chrono::steady_clock;
+    clk::duration t_search{}, t_edit{};
     const float *qbase = reinterpret_cast<const float *>(v->data);
     deg_status s = DEG_OK;
     for (int64_t s0 = (int64_t)d + 1; s0 < n;) {
         const int64_t nv = s0;
         const int64_t bsz = block_size(nv, cap, n - s0);
+        const clk::time_point t0 = clk::now();
         if ((s = upload()) != DEG_OK) return s;
         s = deg_search(v, &g, qbase + s0 * (int64_t)v->row_stride, bsz, v->row_stride, d_seeds, 1,
                        k, p->eps_ext, &o, d_ids, d_ds, d_stats, d_ws, ws, st);
@@ -324,6 +383,7 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
                            st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess)
             return DEG_ERR_HIP;
+        const clk::time_point t1 = clk::now();
         ++blocks;
         searches += bsz;
         for (int64_t i = 0; i < bsz; ++i) {
@@ -336,16 +396,22 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
                                h_ids + i * k, h_ds + i * k, ns, phase2))
                 return DEG_ERR_UNSUPPORTED;  // the search result cannot supply d neighbours
         }
+        t_search += t1 - t0;
+        t_edit += clk::now() - t1;
         s0 += bsz;
     }
     if ((s = upload()) != DEG_OK) return s;
     if (hipStreamSynchronize(st) != hipSuccess) return DEG_ERR_HIP;
-    if (weights) memcpy(weights, G.w.data(), sizeof(float) * (size_t)n * d);
+    if (weights)
+        for (int64_t a = 0; a < n; ++a)
+            for (int j = 0; j < d; ++j) weights[a * d + j] = G.r((int32_t)a)[j].e.w;
     if (counters) {
         counters[0] = blocks;
         counters[1] = searches;
         counters[2] = phase2;
         counters[3] = lossy;
+        counters[4] = std::chrono::duration_cast<std::chrono::microseconds>(t_search).count();
+        counters[5] = std::chrono::duration_cast<std::chrono::microseconds>(t_edit).count();
     }
     return DEG_OK;
 }
