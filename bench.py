@@ -371,7 +371,10 @@ def run_build(a):
     gt = None
     stored = ROOT / "data" / "cfg2.deg"
     graphs = {("built_b%d" % b): g for b, (g, _) in builds.items()}
-    if n == 1_000_000 and stored.exists():
+    if a.no_quality:
+        graphs = {}
+        meta = {}
+    elif n == 1_000_000 and stored.exists():
         meta = json.loads((ROOT / "data" / "cfg2.meta.json").read_text())
         gt = np.load(ROOT / "data" / "cfg2.gt.npz")["ids"]
         graphs["stored_sequential_opt"] = dev(load_graph(stored)[0])
@@ -381,8 +384,8 @@ def run_build(a):
         gt = gt_ids.cpu().numpy()
         seed = api.medoid(xb, api.L2)
         meta = {}
-    seeds = torch.full((nq, 1), seed, dtype=torch.int32, device="cuda")
     for name, g in graphs.items():
+        seeds = torch.full((nq, 1), seed, dtype=torch.int32, device="cuda")
         G = api.DeviceGraph(g)
         rows = []
         for eps in (0.0, 0.04, 0.08, 0.1, 0.12, 0.14, 0.16, 0.18, 0.2, 0.22, 0.25, 0.3):
@@ -796,6 +799,8 @@ def main(argv=None):
     ap.add_argument("--build", action="store_true",
                     help="time graph construction with block-batched searches (1M x 128, d=30)")
     ap.add_argument("--build-n", type=int, default=0, help="construction: first N vectors only")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="construction: skip the search-quality sweeps of the built graphs")
     ap.add_argument("--build-batch", type=lambda s: [int(x) for x in s.split(",")],
                     default=[16384], help="construction: block limits (comma list)")
     ap.add_argument("--knn", action="store_true",

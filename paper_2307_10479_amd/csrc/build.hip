@@ -32,77 +32,91 @@ namespace {
 
 // One FP32 distance in the library's fixed order: 32 partial sums, the
 // 4-dim chunk c feeding partial c mod 32 with fused multiply-adds in
-// increasing dim order, then the halving tree over the partials.
-float dist_c32x4(const float *x, const float *q, int m, int metric) {
-    float p[32];
-    for (int i = 0; i < 32; ++i) p[i] = 0.0f;
-    for (int i = 0; i < m; ++i) {
-        const int c = (i >> 2) & 31;
-        if (metric == DEG_METRIC_L2) {
-            const float t = x[i] - q[i];
-            p[c] = fmaf(t, t, p[c]);
-        } else {
-            p[c] = fmaf(x[i], q[i], p[c]);
+// increasing dim order, then the halving tree over the partials. The loops
+// run over the 32 partials innermost (independent chains); each partial still
+// takes its terms in increasing dim order.
+template <bool L2>
+inline void c32x4_block(const float *x, const float *q, float *p, int base, int m, bool full) {
+    for (int j = 0; j < 4; ++j)
+        for (int c = 0; c < 32; ++c) {
+            const int i = base + 4 * c + j;
+            if (full || i < m) {
+                if (L2) {
+                    const float t = x[i] - q[i];
+                    p[c] = fmaf(t, t, p[c]);
+                } else {
+                    p[c] = fmaf(x[i], q[i], p[c]);
+                }
+            }
         }
-    }
-    for (int w = 16; w >= 1; w >>= 1)
-        for (int i = 0; i < w; ++i) p[i] = p[i] + p[i + w];
-    return metric == DEG_METRIC_L2 ? p[0] : 1.0f - p[0];
 }
 
-// Host copy of the growing graph. A vertex owns one 64-byte aligned record: a
-// header (neighbour count, block of the last change) and up to d (neighbour,
-// weight) slots filled from the front, so one fetch brings everything an edit
-// reads; removal keeps the order of the remaining entries.
-union Cell {
-    struct {
-        int32_t id;
-        float w;
-    } e;
-    struct {
-        int32_t cnt;
-        int32_t stamp;
-    } h;
-};
+template <bool L2>
+float c32x4(const float *x, const float *q, int m) {
+    float p[32];
+    for (int i = 0; i < 32; ++i) p[i] = 0.0f;
+    int base = 0;
+    for (; base + 128 <= m; base += 128) c32x4_block<L2>(x, q, p, base, m, true);
+    if (base < m) c32x4_block<L2>(x, q, p, base, m, false);
+    for (int w = 16; w >= 1; w >>= 1)
+        for (int i = 0; i < w; ++i) p[i] = p[i] + p[i + w];
+    return L2 ? p[0] : 1.0f - p[0];
+}
 
+float dist_c32x4(const float *x, const float *q, int m, int metric) {
+    return metric == DEG_METRIC_L2 ? c32x4<true>(x, q, m) : c32x4<false>(x, q, m);
+}
+
+// Host copy of the growing graph. A vertex owns one 64-byte aligned record of
+// 32-bit words: neighbour count, block of the last change, d neighbour ids and
+// d weights (filled from the front; removal keeps the order of the remaining
+// entries), so one fetch brings everything an edit reads. The records live in
+// pinned host memory: the device gathers the changed rows from them directly.
 struct HostGraph {
     int64_t n;
     int d;
-    int64_t stride;  // cells per record, a multiple of 8 (64 bytes)
-    Cell *cells = nullptr;
+    int64_t stride;  // words per record, a multiple of 16 (64 bytes)
+    int32_t *words = nullptr;
     std::vector<int32_t> dirty;  // records changed since the last upload
     int32_t block = 0;
     bool broken = false;
 
-    HostGraph(int64_t n_, int d_) : n(n_), d(d_), stride(((int64_t)d_ + 1 + 7) / 8 * 8) {
-        cells = static_cast<Cell *>(aligned_alloc(64, sizeof(Cell) * (size_t)(n * stride)));
-        if (!cells) return;
+    HostGraph(int64_t n_, int d_) : n(n_), d(d_), stride((2 + 2 * (int64_t)d_ + 15) / 16 * 16) {
+        if (hipHostMalloc((void **)&words, sizeof(int32_t) * (size_t)(n * stride)) != hipSuccess) {
+            words = nullptr;
+            return;
+        }
         for (int64_t a = 0; a < n; ++a) {
-            Cell *c = cells + a * stride;
-            c[0].h.cnt = 0;
-            c[0].h.stamp = -1;
-            for (int j = 1; j <= d; ++j) c[j].e = {-1, 0.0f};
+            int32_t *x = words + a * stride;
+            x[0] = 0;
+            x[1] = -1;
+            for (int j = 0; j < d; ++j) x[2 + j] = -1;
+            float *w = reinterpret_cast<float *>(x + 2 + d);
+            for (int j = 0; j < d; ++j) w[j] = 0.0f;
         }
     }
-    ~HostGraph() { free(cells); }
+    ~HostGraph() {
+        if (words) (void)hipHostFree(words);
+    }
     HostGraph(const HostGraph &) = delete;
     HostGraph &operator=(const HostGraph &) = delete;
 
-    Cell *rec(int32_t a) { return cells + (int64_t)a * stride; }
-    int32_t &cnt(int32_t a) { return rec(a)[0].h.cnt; }
-    Cell *r(int32_t a) { return rec(a) + 1; }
+    int32_t *rec(int32_t a) { return words + (int64_t)a * stride; }
+    int32_t &cnt(int32_t a) { return rec(a)[0]; }
+    int32_t *ids(int32_t a) { return rec(a) + 2; }
+    float *ws(int32_t a) { return reinterpret_cast<float *>(rec(a) + 2 + d); }
     void touch(int32_t a) {
-        int32_t &st = rec(a)[0].h.stamp;
+        int32_t &st = rec(a)[1];
         if (st != block) {
             st = block;
             dirty.push_back(a);
         }
     }
     int find(int32_t a, int32_t b) {
-        const Cell *x = r(a);
+        const int32_t *x = ids(a);
         const int c = cnt(a);
         for (int j = 0; j < c; ++j)
-            if (x[j].e.id == b) return j;
+            if (x[j] == b) return j;
         return -1;
     }
     void half_add(int32_t a, int32_t b, float wt) {
@@ -111,7 +125,9 @@ struct HostGraph {
             broken = true;
             return;
         }
-        r(a)[c++].e = {b, wt};
+        ids(a)[c] = b;
+        ws(a)[c] = wt;
+        ++c;
         touch(a);
     }
     void half_remove(int32_t a, int32_t b) {
@@ -120,10 +136,16 @@ struct HostGraph {
             broken = true;
             return;
         }
-        Cell *x = r(a);
+        int32_t *x = ids(a);
+        float *w = ws(a);
         int32_t &c = cnt(a);
-        for (; j + 1 < c; ++j) x[j] = x[j + 1];
-        x[--c].e = {-1, 0.0f};
+        for (; j + 1 < c; ++j) {
+            x[j] = x[j + 1];
+            w[j] = w[j + 1];
+        }
+        --c;
+        x[c] = -1;
+        w[c] = 0.0f;
         touch(a);
     }
     void add_edge(int32_t a, int32_t b, float wt) {
@@ -134,11 +156,17 @@ struct HostGraph {
         half_add(a, b, wt);
         half_add(b, a, wt);
     }
-    void remove_edge(int32_t a, int32_t b) {
-        half_remove(a, b);
-        half_remove(b, a);
-    }
 };
+
+// Starts the fetches of the records a search result's walk will read (issued a
+// few vertices ahead of the walk: the results of a block are all known).
+void prefetch_result(HostGraph &G, const int32_t *ids, int k) {
+    const size_t rec_bytes = sizeof(int32_t) * (size_t)(2 + 2 * G.d);
+    for (int i = 0; i < k && ids[i] >= 0; ++i) {
+        const char *a = reinterpret_cast<const char *>(G.rec(ids[i]));
+        for (size_t o = 0; o < rec_bytes; o += 64) __builtin_prefetch(a + o);
+    }
+}
 
 // Steps 3-6 of Sec. 5.2 for vertex v given its search result (sorted ids and
 // distances, ns entries). Returns false when the result cannot supply d
@@ -150,11 +178,7 @@ bool extend_vertex(HostGraph &G, const float *vec, int64_t vs, int m, int metric
     float Ud[128];
     bool pend[128];  // U[t] is a cut edge's far end whose distance is not computed yet
     int nu = 0;
-    // the candidates' records are read in turn below: start their fetches now
-    for (int i = 0; i < ns; ++i) {
-        const char *a = reinterpret_cast<const char *>(G.rec(ids[i]));
-        for (size_t o = 0; o < sizeof(Cell) * (size_t)(d + 1); o += 64) __builtin_prefetch(a + o);
-    }
+    const size_t rec_bytes = sizeof(int32_t) * (size_t)(2 + 2 * d);
     // membership in U: a 256-bit filter of hashed ids answers most lookups, the
     // short list the rest
     uint64_t filt[4] = {0, 0, 0, 0};
@@ -190,14 +214,15 @@ bool extend_vertex(HostGraph &G, const float *vec, int64_t vs, int m, int metric
             // tentative neighbours u of v adjacent to b (the edge stays out when
             // it is longer than both other sides of such a triangle), and b's
             // longest edge to a vertex outside U (equal weights: smaller id)
-            const Cell *x = G.r(b);
+            const int32_t *x = G.ids(b);
+            const float *xw = G.ws(b);
             const int cb = G.cnt(b);
             bool ok = true;
             int32_t far = -1;
             float fw = -INFINITY;
             for (int j = 0; j < cb; ++j) {
-                const int32_t c = x[j].e.id;
-                const float wt = x[j].e.w;
+                const int32_t c = x[j];
+                const float wt = xw[j];
                 const int t = in_u(c);
                 if (t >= 0) {
                     if (pass == 0) {
@@ -213,7 +238,7 @@ bool extend_vertex(HostGraph &G, const float *vec, int64_t vs, int m, int metric
             // the far end's record and vector are needed only at the end (nothing
             // in between reads its row: it is in U from here on)
             const char *fr = reinterpret_cast<const char *>(G.rec(far));
-            for (size_t o = 0; o < sizeof(Cell) * (size_t)(d + 1); o += 64) __builtin_prefetch(fr + o);
+            for (size_t o = 0; o < rec_bytes; o += 64) __builtin_prefetch(fr + o);
             const char *fv = reinterpret_cast<const char *>(vec + (size_t)far * vs);
             for (int o = 0; o < m * 4; o += 64) __builtin_prefetch(fv + o);
             G.half_remove(b, far);
@@ -238,14 +263,15 @@ __global__ void fill_i32(int32_t *p, int64_t n, int32_t val) {
         p[i] = val;
 }
 
-// rows[r] (d ints) -> adj[ids[r]]
-__global__ void scatter_rows(int32_t *adj, int d, const int32_t *ids, const int32_t *rows,
-                             int64_t nrows) {
+// adj[row[r]] <- the neighbour ids of record row[r] (read from pinned host memory)
+__global__ void gather_rows(int32_t *adj, int d, const int32_t *rows, int64_t nrows,
+                            const int32_t *records, int64_t stride) {
     const int64_t total = nrows * d;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = i / d;
-        adj[(int64_t)ids[r] * d + (i - r * d)] = rows[i];
+        const int64_t a = rows[r];
+        adj[a * d + (i - r * d)] = records[a * stride + 2 + (i - r * d)];
     }
 }
 
@@ -257,11 +283,15 @@ int64_t block_size(int64_t nv, int64_t batch, int64_t left) {
     return b;
 }
 
-// Device and pinned host buffers of one build, freed on every return path.
+// Device and pinned host buffers of one build, freed on every return path once
+// the stream has drained (an error may leave work in flight).
 struct Buffers {
+    hipStream_t st;
     void *dev[6] = {};
     void *host[4] = {};
+    explicit Buffers(hipStream_t s) : st(s) {}
     ~Buffers() {
+        (void)hipStreamSynchronize(st);
         for (void *p : dev)
             if (p) (void)hipFree(p);
         for (void *p : host)
@@ -288,7 +318,7 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
     HostGraph G(n, d);
-    if (!G.cells) return DEG_ERR_HIP;
+    if (!G.words) return DEG_ERR_HIP;
     // the smallest DEG: the complete graph on vertices 0..d
     for (int32_t a = 0; a <= d; ++a)
         for (int32_t b = a + 1; b <= d; ++b)
@@ -304,13 +334,13 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     const size_t ws = deg_search_workspace_bytes(v, &g, cap, k, &o);
     if (ws == 0) return DEG_ERR_UNSUPPORTED;
 
-    Buffers B;
-    int32_t *d_seeds, *d_ids, *d_stats, *d_rowids, *d_rows;
+    Buffers B(st);
+    int32_t *d_seeds, *d_ids, *d_stats, *d_rows;
     float *d_ds;
     int32_t *h_ids, *h_stats, *h_up;
     float *h_ds;
-    // dirty rows per block: at most 3 per new vertex (the vertex and both ends of
-    // each cut edge are d/2 pairs: v, and d distinct others)
+    // changed records per block: at most d + 1 per new vertex (the vertex and the
+    // d distinct ends of its d/2 cut edges), and the smallest DEG's before the first
     const int64_t up_cap = cap * (d + 1) + d + 1;
     if (hipMalloc((void **)&d_seeds, sizeof(int32_t) * cap) != hipSuccess) return DEG_ERR_HIP;
     B.dev[0] = d_seeds;
@@ -320,11 +350,10 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     B.dev[2] = d_ds;
     if (hipMalloc((void **)&d_stats, sizeof(int32_t) * cap * 4) != hipSuccess) return DEG_ERR_HIP;
     B.dev[3] = d_stats;
-    if (hipMalloc((void **)&d_rows, sizeof(int32_t) * up_cap * (d + 1) + ws) != hipSuccess)
-        return DEG_ERR_HIP;
+    const size_t rows_bytes = (sizeof(int32_t) * up_cap + 255) / 256 * 256;
+    if (hipMalloc((void **)&d_rows, rows_bytes + ws) != hipSuccess) return DEG_ERR_HIP;
     B.dev[4] = d_rows;
-    d_rowids = d_rows + up_cap * d;
-    void *d_ws = reinterpret_cast<char *>(d_rows) + sizeof(int32_t) * up_cap * (d + 1);
+    void *d_ws = reinterpret_cast<char *>(d_rows) + rows_bytes;
     if (hipHostMalloc((void **)&h_ids, sizeof(int32_t) * cap * k) != hipSuccess) return DEG_ERR_HIP;
     B.host[0] = h_ids;
     if (hipHostMalloc((void **)&h_ds, sizeof(float) * cap * k) != hipSuccess) return DEG_ERR_HIP;
@@ -332,31 +361,29 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     if (hipHostMalloc((void **)&h_stats, sizeof(int32_t) * cap * 4) != hipSuccess)
         return DEG_ERR_HIP;
     B.host[2] = h_stats;
-    if (hipHostMalloc((void **)&h_up, sizeof(int32_t) * up_cap * (d + 1)) != hipSuccess)
-        return DEG_ERR_HIP;
+    if (hipHostMalloc((void **)&h_up, sizeof(int32_t) * up_cap) != hipSuccess) return DEG_ERR_HIP;
     B.host[3] = h_up;
+    int32_t *d_records = nullptr;
+    if (hipHostGetDevicePointer((void **)&d_records, G.words, 0) != hipSuccess || !d_records)
+        return DEG_ERR_HIP;
 
     fill_i32<<<256, 256, 0, st>>>(adjacency, n * d, -1);
     fill_i32<<<64, 256, 0, st>>>(d_seeds, cap, 0);
 
-    // the changed rows go to the device: packed rows first, their ids after
+    // the changed rows go to the device: their vertex ids are copied, the rows
+    // themselves are read from the records by the gather kernel (the host edits
+    // them again only after the stream has been synchronised)
     auto upload = [&]() -> deg_status {
         const int64_t nr = (int64_t)G.dirty.size();
         if (nr == 0) return DEG_OK;
         if (nr > up_cap) return DEG_ERR_HIP;
-        for (int64_t r = 0; r < nr; ++r) {
-            const Cell *x = G.r(G.dirty[r]);
-            for (int j = 0; j < d; ++j) h_up[r * d + j] = x[j].e.id;
-            h_up[up_cap * d + r] = G.dirty[r];
-        }
-        if (hipMemcpyAsync(d_rows, h_up, sizeof(int32_t) * nr * d, hipMemcpyHostToDevice, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(d_rowids, h_up + up_cap * d, sizeof(int32_t) * nr,
-                           hipMemcpyHostToDevice, st) != hipSuccess)
+        memcpy(h_up, G.dirty.data(), sizeof(int32_t) * nr);
+        if (hipMemcpyAsync(d_rows, h_up, sizeof(int32_t) * nr, hipMemcpyHostToDevice, st) !=
+            hipSuccess)
             return DEG_ERR_HIP;
         int blocks = (int)((nr * d + 255) / 256);
-        if (blocks > 4096) blocks = 4096;
-        scatter_rows<<<blocks, 256, 0, st>>>(adjacency, d, d_rowids, d_rows, nr);
+        if (blocks > 8192) blocks = 8192;
+        gather_rows<<<blocks, 256, 0, st>>>(adjacency, d, d_rows, nr, d_records, G.stride);
         G.dirty.clear();
         ++G.block;
         return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
@@ -386,7 +413,10 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
         const clk::time_point t1 = clk::now();
         ++blocks;
         searches += bsz;
+        constexpr int AHEAD = 2;
+        for (int64_t i = 0; i < AHEAD && i < bsz; ++i) prefetch_result(G, h_ids + i * k, k);
         for (int64_t i = 0; i < bsz; ++i) {
+            if (i + AHEAD < bsz) prefetch_result(G, h_ids + (i + AHEAD) * k, k);
             const int32_t fl = h_stats[i * 4 + 2];
             if (fl & DEG_FLAG_BAD_ID) return DEG_ERR_HIP;  // the device graph is corrupt
             if (fl & DEG_FLAG_QUEUE_OVERFLOW) ++lossy;
@@ -404,7 +434,7 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     if (hipStreamSynchronize(st) != hipSuccess) return DEG_ERR_HIP;
     if (weights)
         for (int64_t a = 0; a < n; ++a)
-            for (int j = 0; j < d; ++j) weights[a * d + j] = G.r((int32_t)a)[j].e.w;
+            for (int j = 0; j < d; ++j) weights[a * d + j] = G.ws((int32_t)a)[j];
     if (counters) {
         counters[0] = blocks;
         counters[1] = searches;

@@ -3,8 +3,8 @@
     python -m paper_2307_10479_amd.prof_summary trace <kt_results.db> [name filter]
     python -m paper_2307_10479_amd.prof_summary pmc <pmc_results.db> [name filter]
 
-`trace` prints, per kernel name, the dispatch count, the average, minimum and
-maximum duration (ms) and the VGPR / SGPR / LDS figures of its launches; `pmc`
+`trace` prints, per kernel name, the dispatch count, the total, average, minimum
+and maximum duration (ms) and the VGPR / SGPR / LDS figures of its launches; `pmc`
 prints every dispatch's counter values. Reads the SQLite views rocprofv3 writes.
 """
 from __future__ import annotations
@@ -27,12 +27,13 @@ def trace(db: str, filt: str = "") -> str:
         a["tot"] += dur
         a["mn"] = dur if a["mn"] is None else min(a["mn"], dur)
         a["mx"] = max(a["mx"], dur)
-    out = ["| kernel | calls | avg ms | min ms | max ms | VGPR | AGPR | SGPR | LDS B | scratch B | waves |",
-           "|---|---|---|---|---|---|---|---|---|---|---|"]
+    out = ["| kernel | calls | total ms | avg ms | min ms | max ms | VGPR | AGPR | SGPR | LDS B | "
+           "scratch B | waves |",
+           "|---|---|---|---|---|---|---|---|---|---|---|---|"]
     for name, a in sorted(agg.items(), key=lambda kv: -kv[1]["tot"]):
-        out.append("| `%s` | %d | %.3f | %.3f | %.3f | %d | %d | %d | %d | %d | %d |" % (
-            name[:90], a["n"], a["tot"] / a["n"] / 1e6, a["mn"] / 1e6, a["mx"] / 1e6, a["vg"], a["ag"],
-            a["sg"], a["lds"], a["scr"], a["waves"]))
+        out.append("| `%s` | %d | %.3f | %.3f | %.3f | %.3f | %d | %d | %d | %d | %d | %d |" % (
+            name[:90], a["n"], a["tot"] / 1e6, a["tot"] / a["n"] / 1e6, a["mn"] / 1e6,
+            a["mx"] / 1e6, a["vg"], a["ag"], a["sg"], a["lds"], a["scr"], a["waves"]))
     return "\n".join(out)
 
 
