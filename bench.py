@@ -33,8 +33,8 @@ import numpy as np
 ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
-EPS_SWEEP = [0.0, 0.05, 0.1, 0.12, 0.14, 0.15, 0.16, 0.17, 0.18, 0.19, 0.2, 0.22, 0.25, 0.3]
-BL_EPS_STEPS = [0.0, 0.02, 0.04, 0.06]  # eps above the B operating point tried with the stop model
+EPS_SWEEP = [0.0, 0.05, 0.08, 0.09, 0.1, 0.11, 0.12, 0.13, 0.14, 0.15, 0.16, 0.17, 0.18, 0.19, 0.2, 0.22, 0.25, 0.3]
+BL_EPS_STEPS = [0.0, 0.01, 0.02, 0.03, 0.04, 0.06]  # eps above the B operating point tried with the stop model
 BL_POOL = 20  # rerank pool of BL on the mixed stream (one size for the whole launch)
 BL_LONG_HOPS = (1024, 2048, 3072)  # hops from which a second (lower) stop threshold applies
 BL_TAU_LONG = (0.2, 0.3, 0.4, 0.5, 0.6, 0.8)
@@ -803,6 +803,9 @@ def main(argv=None):
                     help="construction: skip the search-quality sweeps of the built graphs")
     ap.add_argument("--build-batch", type=lambda s: [int(x) for x in s.split(",")],
                     default=[16384], help="construction: block limits (comma list)")
+    ap.add_argument("--built-graph", action="store_true",
+                    help="cfg2: search the graph of the batched GPU construction instead of the "
+                         "stored one")
     ap.add_argument("--knn", action="store_true",
                     help="time the brute-force ground truth (matrix cores) instead of the search")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -843,6 +846,17 @@ def main(argv=None):
     xb = dev(base)
     s32 = api.VectorStore(xb, "f32", metric)
     s16 = api.VectorStore(xb, "bf16", metric)
+    graph_src = "stored: the oracle's construction, one vertex at a time, with optimizeEdge"
+    if a.built_graph:
+        # the same workload on the graph of the batched construction (no optimizeEdge),
+        # built here on the GPU outside the timed region
+        adj_t, _, bc = api.build_graph(s32, base, d, 2 * d, 0.2, 16384)
+        torch.cuda.synchronize()
+        adj = adj_t.cpu().numpy()
+        del adj_t
+        graph_src = ("built: batched construction on the GPU (block limit 16384, k_ext %d, "
+                     "eps_ext 0.2, no optimizeEdge), %d blocks" % (2 * d, bc["blocks"]))
+        log("graph built in-process: %s" % bc)
     G = api.DeviceGraph(dev(adj))
     Q = dev(q)
     seed = api.medoid(xb, metric)
@@ -1202,6 +1216,7 @@ def main(argv=None):
         "config": {
             "workload": "%s: %s" % (a.workload, WORKLOADS[a.workload]["desc"]),
             "method": "BL: BF16 traversal + FP32 rerank + learned early stop",
+            "graph": graph_src,
             "k": k, "eps": head["eps"], "queue_cap": head["L"], "recall@10": round(head["recall"], 5),
             "tau": tau, "tau_long": opBL.get("tau_long"), "long_hops": opBL.get("long_hops"),
             "stop_interval": a.stop_interval, "tuned": tuned,
