@@ -83,3 +83,16 @@ def test_build_result_too_small_is_an_error(A):
     store = A.VectorStore(torch.from_numpy(x).cuda(), "f32", oracle.L2)
     with pytest.raises(A.DegError):
         A.build_graph(store, x, 10, 2, 0.0, 16)
+
+
+def test_build_full_size_invariants(A):
+    # all 1,000,000 x 128 vectors of the integer workload, degree 30, blocks of up to
+    # 16,384: the graph of Sec. 5.1 (even-regular, undirected, no loops, connected, no
+    # bridges) and every edge weight equal to the oracle's FP32 distance; no search
+    # lost a candidate to the capacity of S
+    x = np.ascontiguousarray(synth.cfg2()[0])
+    say("build cfg2 full size")
+    adj, w, cnt = gpu_build(A, x, 30, 60, 0.2, 16384)
+    say("build cfg2 full size counters", cnt)
+    assert cnt["lossy"] == 0 and cnt["searches"] == len(x) - 31
+    check(adj, w, x, oracle.L2)
