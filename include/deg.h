@@ -330,6 +330,23 @@ deg_status deg_build_graph(const deg_vectors *v, const float *host_vectors, int6
                            const deg_build_params *p, int32_t *adjacency, float *weights,
                            int64_t *counters, void *stream);
 
+/*
+ * MRNG conformity of every edge (Algorithm 2): the selection step of the
+ * dynamic edge optimisation (Algorithm 5 optimises a vertex's edges that fail
+ * it). Edge (v1, v2) fails when a common neighbour u of v1 and v2 has
+ * max(w(v1, u), w(v2, u)) < w(v1, v2); only stored weights are compared.
+ *   g          device adjacency (degree <= 128; id -1 marks an empty slot)
+ *   weights    device, n rows of w_stride FP32: weights[v][j] is the weight of
+ *              the edge to adj[v][j] (as deg_build_graph returns them)
+ *   out_ok     device, n x degree bytes: 1 the edge passes, 0 it fails, 255 the
+ *              slot is empty (or holds an id outside [0, n))
+ *   out_fail_count nullable device int64: the number of failing entries (each
+ *              undirected edge is counted from both ends)
+ * Asynchronous on `stream`; allocates nothing.
+ */
+deg_status deg_graph_check_mrng(const deg_graph *g, const float *weights, int64_t w_stride,
+                                uint8_t *out_ok, int64_t *out_fail_count, void *stream);
+
 /* Reduced-precision stores. BF16: round to nearest even. FP8: per row
  * scale = max|x| / 448 (1 if the row is zero), code = E4M3 round to nearest
  * even of x / scale, saturating at 448. Rows beyond dim are zero-filled up to

@@ -16,7 +16,7 @@ CSRC = PKG / "csrc"
 BUILD = PKG / "_build"
 LIB = PKG / "libdeg.so"
 SOURCES = ["search.hip", "search_f32.hip", "search_bf16.hip", "search_fp8.hip", "util.hip",
-           "knn.hip", "mlp.hip", "build.hip"]
+           "knn.hip", "mlp.hip", "build.hip", "graph_check.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I" + str(ROOT / "include"),
          "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
