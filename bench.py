@@ -89,11 +89,11 @@ SEARCH_SOURCES = ("host_util.h", "mlp_device.h", "search.hip", "search_bf16.hip"
 
 
 def kernel_source_digest() -> str:
-    """SHA-256 over the sources the search kernel is built from and the C header."""
+    """SHA-256 over the sources the search kernel and its launch are built from."""
     import hashlib
     h = hashlib.sha256()
     csrc = ROOT / "paper_2307_10479_amd" / "csrc"
-    files = [csrc / f for f in SEARCH_SOURCES] + [ROOT / "include" / "deg.h"]
+    files = [csrc / f for f in SEARCH_SOURCES]
     for f in files:
         h.update(f.name.encode())
         h.update(f.read_bytes())
@@ -982,7 +982,7 @@ def main(argv=None):
         train_eps = (bl_eps if a.train_eps == "op"
                      else sorted(set([0.0, opB["eps"], min(0.4, opB["eps"] * 2 + 0.02)])))
         tn = tuned["B"]
-        intervals = (a.stop_interval, 2 * a.stop_interval)
+        intervals = (a.stop_interval, 2 * a.stop_interval, 4 * a.stop_interval, 8 * a.stop_interval)
         models = {}
         for itv in intervals:
             # the features depend on the checkpoint spacing: one network per interval
