@@ -180,17 +180,27 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
     const int64_t per = (P.n + P.nslices - 1) / P.nslices;
     const int64_t n0 = (int64_t)slice * per;
     const int64_t n1 = min(P.n, n0 + per);
-    // LDS: per-row list counters, distance thresholds and excluded ids, then the
-    // operand tiles
+    // LDS: per-row list counters, distance thresholds and excluded ids, two block
+    // flags, then the operand tiles
     int32_t *rcnt = reinterpret_cast<int32_t *>(smem);               // KQ
     float *rthr = reinterpret_cast<float *>(smem + 4 * KQ);          // KQ
     int32_t *rex = reinterpret_cast<int32_t *>(smem + 8 * KQ);       // KQ
-    unsigned char *tiles = smem + 12 * KQ;
+    // block flags: [0] a list came near its capacity this tile, [1] a threshold changed
+    int32_t *bflag = reinterpret_cast<int32_t *>(smem + 12 * KQ);
+    unsigned char *tiles = smem + 12 * KQ + 16;
     for (int i = t; i < KQ; i += 256) {
         rcnt[i] = 0;
         rthr[i] = __builtin_inff();
         rex[i] = (P.exclude && q0 + i < P.nq) ? P.exclude[q0 + i] : -1;
     }
+    if (t < 4) bflag[t] = 0;
+    // the distance thresholds of this lane's accumulator rows, held in registers and
+    // re-read from LDS only after a cut changed one
+    float thr[2][16];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int v = 0; v < 16; ++v) thr[bi][v] = __builtin_inff();
     // query norms of the rows this lane's accumulator registers hold
     float qn[2][16];
 #pragma unroll
@@ -389,7 +399,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
                     else
                         d = __fsub_rn(1.0f, dot);
                     acc[bi][bj][v] = d;
-                    const bool ok = cid[bj] < n1 && q0 + row < P.nq && d <= rthr[row];
+                    const bool ok = cid[bj] < n1 && q0 + row < P.nq && d <= thr[bi][v];
                     pm |= ok ? (1u << v) : 0u;
                 }
                 passm[bi][bj] = pm;
@@ -406,6 +416,7 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
                         const int row = 64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
                         if ((int32_t)cid[bj] == rex[row]) continue;  // kept out of this query's answer
                         const int pos = atomicAdd(&rcnt[row], 1);
+                        if (pos + 1 > P.cap - KN) bflag[0] = 1;
                         P.lists[((q0 + row) * P.nslices + slice) * P.cap + pos] =
                             make_key(acc[bi][bj][v], (int32_t)cid[bj]);
                     }
@@ -413,20 +424,30 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
         __threadfence_block();
         __syncthreads();
         // lists that another tile could overflow are cut to their KC smallest keys
-        for (int rr = 0; rr < KQ / 4; ++rr) {
-            const int row = w * (KQ / 4) + rr;
-            int c = rcnt[row];
-            if (c > P.cap - KN && q0 + row < P.nq) {
-                uint64_t *lst = P.lists + ((q0 + row) * P.nslices + slice) * P.cap;
-                const uint64_t th = cut_any(lst, c, P.kc, P.cap);
-                if (lane == 0) {
-                    rcnt[row] = c;
-                    rthr[row] = key_dist(th);
+        // (only when an append of this tile came that near)
+        if (bflag[0] != 0) {
+            for (int rr = 0; rr < KQ / 4; ++rr) {
+                const int row = w * (KQ / 4) + rr;
+                int c = rcnt[row];
+                if (c > P.cap - KN && q0 + row < P.nq) {
+                    uint64_t *lst = P.lists + ((q0 + row) * P.nslices + slice) * P.cap;
+                    const uint64_t th = cut_any(lst, c, P.kc, P.cap);
+                    if (lane == 0) {
+                        rcnt[row] = c;
+                        rthr[row] = key_dist(th);
+                    }
                 }
             }
+            __threadfence_block();
+            __syncthreads();
+            if (t == 0) bflag[0] = 0;
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int v = 0; v < 16; ++v)
+                    thr[bi][v] = rthr[64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
+            __syncthreads();
         }
-        __threadfence_block();
-        __syncthreads();
     }
     // final cut to KC and the list sizes
     for (int rr = 0; rr < KQ / 4; ++rr) {
@@ -632,12 +653,12 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
                            q_stride, flag);
         hipLaunchKernelGGL(to_bf16_kernel, dim3(4096), dim3(256), 0, st, base, n, dim, b_stride,
                            BF16_PAD, const_cast<uint16_t *>(P.base16), flag);
-        const size_t lds16 = 12 * KQ + (size_t)KN * BF16_LD * 2;
+        const size_t lds16 = 12 * KQ + 16 + (size_t)KN * BF16_LD * 2;
         void (*t16)(KnnParams) = metric == DEG_METRIC_L2 ? knn_tile_kernel<DEG_METRIC_L2, true>
                                                          : knn_tile_kernel<DEG_METRIC_IP, true>;
         hipLaunchKernelGGL(t16, g1, dim3(256), lds16, st, P);
     }
-    const size_t lds32 = 12 * KQ + (size_t)KCH * (KQ + 1) * 4 + (size_t)KCH * (KN + 1) * 4;
+    const size_t lds32 = 12 * KQ + 16 + (size_t)KCH * (KQ + 1) * 4 + (size_t)KCH * (KN + 1) * 4;
     void (*t32)(KnnParams) = metric == DEG_METRIC_L2 ? knn_tile_kernel<DEG_METRIC_L2, false>
                                                      : knn_tile_kernel<DEG_METRIC_IP, false>;
     hipLaunchKernelGGL(t32, g1, dim3(256), lds32, st, P);
