@@ -200,7 +200,10 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) thr[bi][v] = __builtin_inff();
+        for (int v = 0; v < 16; ++v) {
+            const int row = 64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+            thr[bi][v] = q0 + row < P.nq ? __builtin_inff() : -__builtin_inff();
+        }
     // query norms of the rows this lane's accumulator registers hold
     float qn[2][16];
 #pragma unroll
@@ -380,7 +383,9 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             cid[bj] = b0 + 64 * wn + 32 * bj + (lane & 31);
-            bn[bj] = (METRIC == DEG_METRIC_L2 && cid[bj] < n1) ? P.bnorm[cid[bj]] : 0.0f;
+            // a column past the slice gets a NaN term: its distance fails every test
+            bn[bj] = cid[bj] < n1 ? (METRIC == DEG_METRIC_L2 ? P.bnorm[cid[bj]] : 0.0f)
+                                  : __builtin_nanf("");
         }
         bool any = false;
         uint32_t passm[2][2];
@@ -397,9 +402,9 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
                     if (METRIC == DEG_METRIC_L2)
                         d = __fsub_rn(__fadd_rn(qn[bi][v], bn[bj]), __fmul_rn(2.0f, dot));
                     else
-                        d = __fsub_rn(1.0f, dot);
+                        d = __fadd_rn(__fsub_rn(1.0f, dot), bn[bj]);
                     acc[bi][bj][v] = d;
-                    const bool ok = cid[bj] < n1 && q0 + row < P.nq && d <= thr[bi][v];
+                    const bool ok = d <= thr[bi][v];  // (rows past the queries hold -inf)
                     pm |= ok ? (1u << v) : 0u;
                 }
                 passm[bi][bj] = pm;
@@ -444,8 +449,10 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
 #pragma unroll
             for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                for (int v = 0; v < 16; ++v)
-                    thr[bi][v] = rthr[64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)];
+                for (int v = 0; v < 16; ++v) {
+                    const int row = 64 * wq + 32 * bi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
+                    thr[bi][v] = q0 + row < P.nq ? rthr[row] : -__builtin_inff();
+                }
             __syncthreads();
         }
     }
