@@ -324,6 +324,14 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
     }
     __syncthreads();
 
+    // the norm term of this lane's base columns (a column past the slice gets a NaN
+    // term: its distance fails every test), one tile ahead
+    float bnc[2];
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) {
+        const int64_t c = n0 + 64 * wn + 32 * bj + (lane & 31);
+        bnc[bj] = c < n1 ? (METRIC == DEG_METRIC_L2 ? P.bnorm[c] : 0.0f) : __builtin_nanf("");
+    }
     for (int64_t b0 = n0; b0 < n1; b0 += KN) {
         floatx16 acc[2][2];
 #pragma unroll
@@ -383,9 +391,10 @@ __global__ void __launch_bounds__(256) knn_tile_kernel(KnnParams P) {
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) {
             cid[bj] = b0 + 64 * wn + 32 * bj + (lane & 31);
-            // a column past the slice gets a NaN term: its distance fails every test
-            bn[bj] = cid[bj] < n1 ? (METRIC == DEG_METRIC_L2 ? P.bnorm[cid[bj]] : 0.0f)
-                                  : __builtin_nanf("");
+            bn[bj] = bnc[bj];
+            // the next tile's norm is requested now and used a tile later
+            const int64_t cn = cid[bj] + KN;
+            bnc[bj] = cn < n1 ? (METRIC == DEG_METRIC_L2 ? P.bnorm[cn] : 0.0f) : __builtin_nanf("");
         }
         bool any = false;
         uint32_t passm[2][2];
