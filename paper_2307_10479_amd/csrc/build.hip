@@ -17,6 +17,7 @@
 // schedule. The optional optimizeEdge step (Algorithm 4) is not part of this
 // entry point: its searches depend on each other's edits.
 #include <hip/hip_runtime.h>
+#include <immintrin.h>
 
 #include <math.h>
 #include <stdint.h>
@@ -32,32 +33,61 @@ namespace {
 
 // One FP32 distance in the library's fixed order: 32 partial sums, the
 // 4-dim chunk c feeding partial c mod 32 with fused multiply-adds in
-// increasing dim order, then the halving tree over the partials. The loops
-// run over the 32 partials innermost (independent chains); each partial still
-// takes its terms in increasing dim order.
+// increasing dim order, then the halving tree over the partials.
+// AVX2: a block of 128 dims is four loads of 32 floats (chunks 8g .. 8g + 7,
+// four dims each); an in-register 8 x 4 transpose gives, for each position j
+// in a chunk, one vector of dim j of the eight chunks, so each vector FMA
+// advances eight partials by one term in their own order. (The eight chunks
+// come out in the order 0 2 4 6 1 3 5 7, undone before the tree.) A short last
+// block is zero-padded: fma(0, 0, p) = p, and a partial sum is never -0.
 template <bool L2>
-inline void c32x4_block(const float *x, const float *q, float *p, int base, int m, bool full) {
-    for (int j = 0; j < 4; ++j)
-        for (int c = 0; c < 32; ++c) {
-            const int i = base + 4 * c + j;
-            if (full || i < m) {
-                if (L2) {
-                    const float t = x[i] - q[i];
-                    p[c] = fmaf(t, t, p[c]);
-                } else {
-                    p[c] = fmaf(x[i], q[i], p[c]);
-                }
-            }
+inline void c32x4_block(const float *x, const float *q, __m256 acc[4]) {
+    for (int g = 0; g < 4; ++g) {
+        __m256 X[4], Q[4];
+        for (int u = 0; u < 4; ++u) {
+            X[u] = _mm256_loadu_ps(x + 32 * g + 8 * u);
+            Q[u] = _mm256_loadu_ps(q + 32 * g + 8 * u);
+            if (L2) X[u] = _mm256_sub_ps(X[u], Q[u]);
         }
+        auto tr = [](const __m256 *V, __m256 J[4]) {
+            const __m256 a = _mm256_unpacklo_ps(V[0], V[1]), b = _mm256_unpackhi_ps(V[0], V[1]);
+            const __m256 c = _mm256_unpacklo_ps(V[2], V[3]), d = _mm256_unpackhi_ps(V[2], V[3]);
+            J[0] = _mm256_shuffle_ps(a, c, 0x44);
+            J[1] = _mm256_shuffle_ps(a, c, 0xEE);
+            J[2] = _mm256_shuffle_ps(b, d, 0x44);
+            J[3] = _mm256_shuffle_ps(b, d, 0xEE);
+        };
+        __m256 XJ[4];
+        tr(X, XJ);
+        if (L2) {
+            for (int j = 0; j < 4; ++j) acc[g] = _mm256_fmadd_ps(XJ[j], XJ[j], acc[g]);
+        } else {
+            __m256 QJ[4];
+            tr(Q, QJ);
+            for (int j = 0; j < 4; ++j) acc[g] = _mm256_fmadd_ps(XJ[j], QJ[j], acc[g]);
+        }
+    }
 }
 
 template <bool L2>
 float c32x4(const float *x, const float *q, int m) {
-    float p[32];
-    for (int i = 0; i < 32; ++i) p[i] = 0.0f;
+    __m256 acc[4] = {_mm256_setzero_ps(), _mm256_setzero_ps(), _mm256_setzero_ps(),
+                     _mm256_setzero_ps()};
     int base = 0;
-    for (; base + 128 <= m; base += 128) c32x4_block<L2>(x, q, p, base, m, true);
-    if (base < m) c32x4_block<L2>(x, q, p, base, m, false);
+    for (; base + 128 <= m; base += 128) c32x4_block<L2>(x + base, q + base, acc);
+    if (base < m) {
+        alignas(32) float xt[128], qt[128];
+        for (int i = 0; i < 128; ++i) {
+            xt[i] = base + i < m ? x[base + i] : 0.0f;
+            qt[i] = base + i < m ? q[base + i] : 0.0f;
+        }
+        c32x4_block<L2>(xt, qt, acc);
+    }
+    alignas(32) float v[32], p[32];
+    for (int g = 0; g < 4; ++g) _mm256_store_ps(v + 8 * g, acc[g]);
+    static constexpr int order[8] = {0, 2, 4, 6, 1, 3, 5, 7};
+    for (int g = 0; g < 4; ++g)
+        for (int e = 0; e < 8; ++e) p[8 * g + order[e]] = v[8 * g + e];
     for (int w = 16; w >= 1; w >>= 1)
         for (int i = 0; i < w; ++i) p[i] = p[i] + p[i + w];
     return L2 ? p[0] : 1.0f - p[0];
