@@ -213,13 +213,19 @@ bool extend_vertex(HostGraph &G, const float *vec, int64_t vs, int m, int metric
     // short list the rest
     uint64_t filt[4] = {0, 0, 0, 0};
     auto hbit = [](int32_t x) { return ((uint32_t)x * 0x9E3779B1u) >> 24; };
-    auto in_u = [&](int32_t x) -> int {
-        const uint32_t h = hbit(x);
-        if (!((filt[h >> 6] >> (h & 63)) & 1)) return -1;
+    auto in_u_list = [&](int32_t x) -> int {
         for (int t = 0; t < nu; ++t)
             if (U[t] == x) return t;
         return -1;
     };
+    auto in_u = [&](int32_t x) -> int {
+        const uint32_t h = hbit(x);
+        if (!((filt[h >> 6] >> (h & 63)) & 1)) return -1;
+        return in_u_list(x);
+    };
+    const __m256i iota8 = _mm256_setr_epi32(0, 1, 2, 3, 4, 5, 6, 7);
+    const __m256i bits8 = _mm256_setr_epi32(1, 2, 4, 8, 16, 32, 64, 128);
+    const __m256i golden8 = _mm256_set1_epi32((int)0x9E3779B1u);
     auto push = [&](int32_t x, float dx, bool later) {
         const uint32_t h = hbit(x);
         filt[h >> 6] |= 1ull << (h & 63);
@@ -250,18 +256,55 @@ bool extend_vertex(HostGraph &G, const float *vec, int64_t vs, int m, int metric
             bool ok = true;
             int32_t far = -1;
             float fw = -INFINITY;
-            for (int j = 0; j < cb; ++j) {
-                const int32_t c = x[j];
-                const float wt = xw[j];
-                const int t = in_u(c);
-                if (t >= 0) {
-                    if (pass == 0) {
+            // eight entries at a time (the record holds at least round_up(d, 8) words
+            // past each array, so the loads stay inside it; lanes past the count are
+            // masked): the filter sorts out most entries as outside U, the rest are
+            // looked up exactly; the longest edge to an entry outside U is a maximum
+            // of (weight, -id), so the order of the reduction does not matter
+            const __m256i filt8 = _mm256_loadu_si256(reinterpret_cast<const __m256i *>(filt));
+            for (int j0 = 0; j0 < cb; j0 += 8) {
+                const __m256i c = _mm256_loadu_si256(reinterpret_cast<const __m256i *>(x + j0));
+                const __m256 wt = _mm256_loadu_ps(xw + j0);
+                const __m256i live = _mm256_cmpgt_epi32(_mm256_set1_epi32(cb - j0), iota8);
+                const __m256i h = _mm256_srli_epi32(_mm256_mullo_epi32(c, golden8), 24);
+                const __m256i word = _mm256_permutevar8x32_epi32(filt8, _mm256_srli_epi32(h, 5));
+                const __m256i bit = _mm256_and_si256(
+                    _mm256_srlv_epi32(word, _mm256_and_si256(h, _mm256_set1_epi32(31))),
+                    _mm256_set1_epi32(1));
+                const int livem = _mm256_movemask_ps(_mm256_castsi256_ps(live));
+                const int maybe = _mm256_movemask_ps(_mm256_castsi256_ps(
+                                      _mm256_cmpeq_epi32(bit, _mm256_set1_epi32(1)))) & livem;
+                int outside = livem & ~maybe;
+                for (int mb = maybe; mb; mb &= mb - 1) {
+                    const int e = __builtin_ctz(mb);
+                    const int32_t ce = x[j0 + e];
+                    const int t = in_u_list(ce);
+                    if (t < 0) {
+                        outside |= 1 << e;  // a false positive of the filter
+                    } else if (pass == 0) {
+                        const float we = xw[j0 + e];
                         const float du = dist_of(t);
-                        if (db > (du > wt ? du : wt)) ok = false;
+                        if (db > (du > we ? du : we)) ok = false;
                     }
-                } else if (wt > fw || (wt == fw && c < far)) {
-                    fw = wt;
-                    far = c;
+                }
+                if (outside == 0) continue;
+                // the best (largest weight, then smallest id) of the outside lanes
+                const __m256i om = _mm256_cmpgt_epi32(
+                    _mm256_and_si256(_mm256_set1_epi32(outside), bits8), _mm256_setzero_si256());
+                __m256 w8 = _mm256_blendv_ps(_mm256_set1_ps(-INFINITY), wt, _mm256_castsi256_ps(om));
+                __m256 mx = _mm256_max_ps(w8, _mm256_permute2f128_ps(w8, w8, 1));
+                mx = _mm256_max_ps(mx, _mm256_shuffle_ps(mx, mx, 0x4E));
+                mx = _mm256_max_ps(mx, _mm256_shuffle_ps(mx, mx, 0xB1));
+                const __m256i at = _mm256_and_si256(om, _mm256_castps_si256(_mm256_cmp_ps(w8, mx, _CMP_EQ_OQ)));
+                __m256i id8 = _mm256_blendv_epi8(_mm256_set1_epi32(INT32_MAX), c, at);
+                id8 = _mm256_min_epi32(id8, _mm256_permute2x128_si256(id8, id8, 1));
+                id8 = _mm256_min_epi32(id8, _mm256_shuffle_epi32(id8, 0x4E));
+                id8 = _mm256_min_epi32(id8, _mm256_shuffle_epi32(id8, 0xB1));
+                const float bw = _mm256_cvtss_f32(mx);
+                const int32_t bid = _mm256_cvtsi256_si32(id8);
+                if (bw > fw || (bw == fw && bid < far)) {
+                    fw = bw;
+                    far = bid;
                 }
             }
             if ((pass == 0 && !ok) || far < 0) continue;
