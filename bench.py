@@ -982,7 +982,7 @@ def main(argv=None):
         train_eps = (bl_eps if a.train_eps == "op"
                      else sorted(set([0.0, opB["eps"], min(0.4, opB["eps"] * 2 + 0.02)])))
         tn = tuned["B"]
-        intervals = (a.stop_interval, 2 * a.stop_interval, 4 * a.stop_interval, 8 * a.stop_interval)
+        intervals = tuple(a.stop_interval << i for i in range(5))
         models = {}
         for itv in intervals:
             # the features depend on the checkpoint spacing: one network per interval
