@@ -334,10 +334,12 @@ def run_degree_sweep(a):
 
 def run_build(a):
     """Graph construction throughput (Sec. 5.2 / Algorithm 3 scheme C, no optimizeEdge)
-    on the 1M x 128 workload, degree 30, k_ext 60, eps_ext 0.2: the searches of each
-    block of new vertices run as one persistent launch, the edits on the host in id
-    order. Quality: QPS at recall@10 >= target of the FP32 search on the built graph
-    next to the stored graph (one vertex at a time with optimizeEdge)."""
+    on the 1M x 128 workload (degree 30, k_ext 60, eps_ext 0.2) or, with --workload
+    cfg3, the 1,183,514 x 100 inner-product set (degree 30, k_ext 30): the searches of
+    each block of new vertices run as one persistent launch, the edits on the host in
+    id order. Quality: QPS against recall (recall@10 of the queries; exploration
+    recall@100 on cfg3) of the FP32 search on the built graph next to the stored graph
+    (one vertex at a time with optimizeEdge)."""
     import time
 
     import torch
@@ -347,13 +349,21 @@ def run_build(a):
     from synth.io import load_graph
     api.lib()
     torch.cuda.set_device(0)
-    base, q = synth.cfg2()
-    n = a.build_n or base.shape[0]
+    explore = a.workload == "cfg3"
+    if explore:
+        # 1,183,514 x 100 unit vectors, inner product: quality is exploration recall@100
+        base, qids = synth.cfg3()
+        q = base[qids]
+        d, k_ext, eps_ext, metric, name = 30, 30, 0.2, api.IP, "cfg3"
+    else:
+        base, q = synth.cfg2()
+        d, k_ext, eps_ext, metric, name = 30, 60, 0.2, api.L2, "cfg2"
+    n_full = base.shape[0]
+    n = a.build_n or n_full
     base = np.ascontiguousarray(base[:n])
-    d, k_ext, eps_ext = 30, 60, 0.2
     dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
     xb, Q = dev(base), dev(q)
-    store = api.VectorStore(xb, "f32", api.L2)
+    store = api.VectorStore(xb, "f32", metric)
     builds = {}
     for batch in a.build_batch:
         torch.cuda.synchronize()
@@ -366,46 +376,51 @@ def run_build(a):
             "lossy %d" % (n, batch, sec, n / sec, cnt["blocks"], cnt["search_us"] / 1e6,
                           cnt["edit_us"] / 1e6, cnt["lossy"]))
     # search quality of the built graphs against the stored one-at-a-time graph
-    nq, k = q.shape[0], 10
+    nq, k = q.shape[0], (100 if explore else 10)
     sweeps = {}
     gt = None
-    stored = ROOT / "data" / "cfg2.deg"
+    stored = ROOT / "data" / ("%s.deg" % name)
     graphs = {("built_b%d" % b): g for b, (g, _) in builds.items()}
     if a.no_quality:
         graphs = {}
         meta = {}
-    elif n == 1_000_000 and stored.exists():
-        meta = json.loads((ROOT / "data" / "cfg2.meta.json").read_text())
-        gt = np.load(ROOT / "data" / "cfg2.gt.npz")["ids"]
+    elif n == n_full and stored.exists():
+        meta = json.loads((ROOT / "data" / ("%s.meta.json" % name)).read_text())
+        gt = np.load(ROOT / "data" / ("%s.gt.npz" % name))["ids"]
         graphs["stored_sequential_opt"] = dev(load_graph(stored)[0])
         seed = int(meta["medoid"])
+    elif explore:
+        sys.exit("bench: the exploration quality sweep needs the full cfg3 set and its files")
     else:
         gt_ids, _ = api.knn_bruteforce(xb, Q, k, api.L2)
         gt = gt_ids.cpu().numpy()
         seed = api.medoid(xb, api.L2)
         meta = {}
-    for name, g in graphs.items():
+    for gname, g in graphs.items():
         seeds = torch.full((nq, 1), seed, dtype=torch.int32, device="cuda")
         G = api.DeviceGraph(g)
         rows = []
         for eps in (0.0, 0.04, 0.08, 0.1, 0.12, 0.14, 0.16, 0.18, 0.2, 0.22, 0.25, 0.3):
-            times, (ids, ds, st) = _timed_runs(
-                torch, lambda e=eps: api.search(store, G, Q, seeds, k, e), 1, 3)
+            if explore:
+                fn = lambda e=eps: api.search_indexed(store, G, dev(qids), k, e)
+            else:
+                fn = lambda e=eps: api.search(store, G, Q, seeds, k, e)
+            times, (ids, ds, st) = _timed_runs(torch, fn, 1, 3)
             ms = float(np.median(times))
             r = metrics.recall_at_k(ids.cpu().numpy(), gt, k)
-            rows.append(dict(eps=eps, recall_at_10=round(r, 5), ms=round(ms, 3),
+            rows.append(dict(eps=eps, recall=round(r, 5), ms=round(ms, 3),
                              qps=round(nq / (ms / 1e3), 1)))
-            log("graph %s eps %.2f recall@10 %.4f %.3f ms %.0f QPS" % (name, eps, r, ms,
+            log("graph %s eps %.2f recall@%d %.4f %.3f ms %.0f QPS" % (gname, eps, k, r, ms,
                                                                        nq / (ms / 1e3)))
             if r >= a.recall:
                 break
-        sweeps[name] = rows
+        sweeps[gname] = rows
     cpu = None
     if not a.no_cpu_baseline:
         import oracle
         ns = 12_000
         t0 = time.perf_counter()
-        oracle.build_graph_batched(base[:ns], d, a.build_batch[0], oracle.L2, k_ext=k_ext,
+        oracle.build_graph_batched(base[:ns], d, a.build_batch[0], metric, k_ext=k_ext,
                                    eps_ext=eps_ext, do_opt=False)
         sec = time.perf_counter() - t0
         cpu = dict(value=round(ns / sec, 1), unit="vertices/s", cores=1, kind="oracle",
@@ -418,8 +433,12 @@ def run_build(a):
         "unit": "vertices/s", "n_gpus": 1, "steps": 1, "warmup": 0,
         "ms_per_step": round(head["seconds"] * 1e3, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": "DEG construction, %d x 128 integer vectors, d=30, k_ext=60, "
-                               "eps_ext=0.2, block limit %d" % (n, head_b),
+        "config": {"workload": "DEG construction, %s: %d x %d, %s, d=%d, k_ext=%d, eps_ext=%g, "
+                               "block limit %d; quality: %s" % (
+                                   name, n, base.shape[1], "IP" if explore else "L2", d, k_ext,
+                                   eps_ext, head_b,
+                                   "exploration recall@100 (query vertices as their own seeds)"
+                                   if explore else "recall@10 of the 10,000 queries"),
                    "builds": {str(b): c for b, (_, c) in builds.items()},
                    "stored_graph_build_seconds": meta.get("build_seconds"),
                    "search_quality": sweeps},
