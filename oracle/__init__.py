@@ -102,7 +102,7 @@ def _declare(L):
     L.or_graph_extend_with.argtypes = [P, I64, P, P, I64, I32, F32, I32, I32]
     L.or_build_batched.restype = I32
     L.or_build_batched.argtypes = [P, I64, I64, I64, I32, I32, I32, F32, I32, F32, I32, I32, I64,
-                                   P, P, P]
+                                   I32, P, P, P]
     L.or_build_block_size.restype = I64
     L.or_build_block_size.argtypes = [I64, I64, I64]
     L.or_check_graph.restype = I32
@@ -366,18 +366,19 @@ def build_graph(vec, d, metric=L2, k_ext=60, eps_ext=0.2, k_opt=30, eps_opt=0.00
 
 
 def build_graph_batched(vec, d, batch, metric=L2, k_ext=60, eps_ext=0.2, k_opt=30, eps_opt=0.001,
-                        i_opt=5, do_opt=True):
+                        i_opt=5, do_opt=True, lag=0):
     """Construction in blocks of at most `batch` vertices whose searches all run on
     the graph as it stands when the block starts; the edits then follow in id
-    order (batch = 1 is the one-at-a-time build of Sec. 5.2). Returns adjacency,
-    weights and counters like build_graph."""
+    order (batch = 1 is the one-at-a-time build of Sec. 5.2). With lag = 1 the
+    searches of a block run before the previous block's edits are applied.
+    Returns adjacency, weights and counters like build_graph."""
     vec = _f32(vec)
     n, m = vec.shape
     adj = np.empty((n, d), np.int32)
     w = np.empty((n, d), np.float32)
     cnt = np.zeros(8, np.int64)
     rc = lib().or_build_batched(_p(vec), n, m, m, metric, d, k_ext, eps_ext, k_opt, eps_opt, i_opt,
-                                int(do_opt), batch, _p(adj), _p(w), _p(cnt))
+                                int(do_opt), batch, int(lag), _p(adj), _p(w), _p(cnt))
     if rc:
         raise RuntimeError("or_build_batched failed (%d)" % rc)
     return adj, w, dict(zip(["phase2", "opt_calls", "opt_commit", "opt_revert", "case_a",

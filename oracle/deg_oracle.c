@@ -1495,7 +1495,9 @@ int or_build(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t metric,
  * on the live graph) one by one in id order. A block holds at most `batch`
  * vertices and at most an eighth of the vertices already in the graph (at
  * least one), so early blocks stay small. batch = 1 is the one-at-a-time
- * build. This schedule is the framework's reading, not the paper's.
+ * build. With lag 1 a block's searches run while the previous block's edits
+ * are still pending (they see neither block's vertices); the edits still go
+ * in id order. This schedule is the framework's reading, not the paper's.
  */
 int64_t or_build_block_size(int64_t nv, int64_t batch, int64_t left) {
     int64_t b = nv / 8;
@@ -1507,9 +1509,9 @@ int64_t or_build_block_size(int64_t nv, int64_t batch, int64_t left) {
 
 int or_build_batched(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t metric,
                      int32_t d, int32_t k_ext, float eps_ext, int32_t k_opt, float eps_opt,
-                     int32_t i_opt, int32_t do_opt, int64_t batch, int32_t *out_adj,
-                     float *out_w, int64_t *out_counters) {
-    if (batch < 1 || k_ext < 1) return -1;
+                     int32_t i_opt, int32_t do_opt, int64_t batch, int32_t lag,
+                     int32_t *out_adj, float *out_w, int64_t *out_counters) {
+    if (batch < 1 || k_ext < 1 || lag < 0 || lag > 1) return -1;
     Graph *g = or_graph_create(vec, n, m, vs, metric, d);
     if (!g) return -1;
     if (or_graph_init(g)) {
@@ -1518,22 +1520,48 @@ int or_build_batched(const float *vec, int64_t n, int64_t m, int64_t vs, int32_t
     }
     const int64_t stride = (int64_t)k_ext + 1;
     const int64_t cap = batch < n ? batch : n;
-    Ent *res = (Ent *)malloc(sizeof(Ent) * (size_t)(stride * cap));
-    int64_t *cnt = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    /* two result buffers: with lag 1 a block's results wait while the next block searches */
+    Ent *res[2];
+    int64_t *cnt[2];
+    for (int b = 0; b < 2; ++b) {
+        res[b] = (Ent *)malloc(sizeof(Ent) * (size_t)(stride * cap));
+        cnt[b] = (int64_t *)malloc(sizeof(int64_t) * (size_t)cap);
+    }
     int rc = 0;
-    for (int64_t s = d + 1; s < n && rc == 0;) {
-        const int64_t bsz = or_build_block_size(g->nv, batch, n - s);
-        for (int64_t i = 0; i < bsz; ++i) {
-            int32_t seed = 0;
-            cnt[i] = graph_search(g, &seed, 1, s + i, k_ext, eps_ext, res + i * stride);
+    int64_t pend_s = 0, pend_n = 0; /* the block whose edits are still to come (lag 1) */
+    int cur = 0;
+    for (int64_t s = d + 1; (s < n || pend_n > 0) && rc == 0;) {
+        int64_t bsz = 0;
+        if (s < n) {
+            /* the block's searches see the graph as it stands now: with lag 1 the
+               previous block's vertices are not in it yet */
+            bsz = or_build_block_size(g->nv, batch, n - s);
+            for (int64_t i = 0; i < bsz; ++i) {
+                int32_t seed = 0;
+                cnt[cur][i] = graph_search(g, &seed, 1, s + i, k_ext, eps_ext, res[cur] + i * stride);
+            }
         }
-        for (int64_t i = 0; i < bsz && rc == 0; ++i)
-            if (extend_apply(g, s + i, res + i * stride, cnt[i], k_opt, eps_opt, i_opt, do_opt))
-                rc = -3;
+        if (lag == 1) {
+            const int prv = cur ^ 1;
+            for (int64_t i = 0; i < pend_n && rc == 0; ++i)
+                if (extend_apply(g, pend_s + i, res[prv] + i * stride, cnt[prv][i], k_opt, eps_opt,
+                                 i_opt, do_opt))
+                    rc = -3;
+            pend_s = s;
+            pend_n = bsz;
+            cur = prv;
+        } else {
+            for (int64_t i = 0; i < bsz && rc == 0; ++i)
+                if (extend_apply(g, s + i, res[cur] + i * stride, cnt[cur][i], k_opt, eps_opt,
+                                 i_opt, do_opt))
+                    rc = -3;
+        }
         s += bsz;
     }
-    free(res);
-    free(cnt);
+    for (int b = 0; b < 2; ++b) {
+        free(res[b]);
+        free(cnt[b]);
+    }
     if (rc == 0) {
         or_graph_export(g, out_adj, out_w, NULL);
         if (out_counters) or_graph_counters(g, out_counters);

@@ -203,38 +203,52 @@ def test_batched_build_of_one_is_the_sequential_build(do_opt):
     assert c1 == c2
 
 
-def _batched_by_hand(x, d, batch, k_ext, eps_ext, do_opt, metric=oracle.L2):
+def _batched_by_hand(x, d, batch, k_ext, eps_ext, do_opt, metric=oracle.L2, lag=0):
     # the block schedule driven from outside: each block's searches run through the
     # public RangeSearch on the adjacency exported when the block starts, then the
-    # edits go in id order
+    # edits go in id order (with lag 1: the previous block's edits, after this
+    # block's searches)
     g = oracle.Graph(x, d, metric)
     g.init()
     n = len(x)
     s = d + 1
-    while s < n:
-        b = oracle.build_block_size(g.nv, batch, n - s)
-        adj, _, _ = g.export()
-        ids, ds, _ = oracle.range_search(x, adj, x[s:s + b], [0], k_ext, eps_ext, metric)
-        for i in range(b):
-            live = ids[i] >= 0
-            assert g.extend_with(s + i, ids[i][live], ds[i][live], k_opt=d, do_opt=do_opt) == 0
-        s += b
+    pending = None
+    while s < n or pending is not None:
+        cur = None
+        if s < n:
+            b = oracle.build_block_size(g.nv, batch, n - s)
+            adj, _, _ = g.export()
+            ids, ds, _ = oracle.range_search(x, adj, x[s:s + b], [0], k_ext, eps_ext, metric)
+            cur = (s, ids, ds)
+            s += b
+        todo = [cur] if lag == 0 else [pending]
+        for blk in todo:
+            if blk is None:
+                continue
+            s0, ids, ds = blk
+            for i in range(len(ids)):
+                live = ids[i] >= 0
+                assert g.extend_with(s0 + i, ids[i][live], ds[i][live], k_opt=d, do_opt=do_opt) == 0
+        pending = cur if lag == 1 else None
     adj, w, _ = g.export()
     return adj, w
 
 
-@pytest.mark.parametrize("batch,do_opt,metric", [(16, False, oracle.L2), (64, True, oracle.L2),
-                                                 (1000, False, oracle.IP)])
-def test_batched_build_matches_the_schedule_and_keeps_invariants(batch, do_opt, metric):
+@pytest.mark.parametrize("batch,do_opt,metric,lag", [(16, False, oracle.L2, 0),
+                                                     (64, True, oracle.L2, 0),
+                                                     (1000, False, oracle.IP, 0),
+                                                     (16, False, oracle.L2, 1),
+                                                     (64, True, oracle.IP, 1)])
+def test_batched_build_matches_the_schedule_and_keeps_invariants(batch, do_opt, metric, lag):
     n, d = 900, 10
     x = synth.small_int(22, n, 16, hi=64) if metric == oracle.L2 else synth.small_unit(22, n, 16)
     adj, w, cnt = oracle.build_graph_batched(x, d, batch, metric, k_ext=2 * d, eps_ext=0.2,
-                                             k_opt=d, do_opt=do_opt)
+                                             k_opt=d, do_opt=do_opt, lag=lag)
     chk = oracle.check_graph(adj, x, w, metric)
     assert chk["flags"] == 0, chk
     assert chk["edges"] == n * d // 2 and chk["bridges"] == 0
     assert cnt["err"] == 0
-    a2, w2 = _batched_by_hand(x, d, batch, 2 * d, 0.2, do_opt, metric)
+    a2, w2 = _batched_by_hand(x, d, batch, 2 * d, 0.2, do_opt, metric, lag)
     assert (adj == a2).all() and (w == w2).all()
     # a block's searches do not see each other: with a large batch the graph differs
     # from the one-at-a-time build
