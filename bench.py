@@ -368,7 +368,7 @@ def run_build(a):
     for batch in a.build_batch:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        adj, w, cnt = api.build_graph(store, base, d, k_ext, eps_ext, batch)
+        adj, w, cnt = api.build_graph(store, base, d, k_ext, eps_ext, batch, lag=a.build_lag)
         torch.cuda.synchronize()
         sec = time.perf_counter() - t0
         builds[batch] = (adj, dict(cnt, seconds=round(sec, 3), vertices_per_s=round(n / sec, 1)))
@@ -434,9 +434,9 @@ def run_build(a):
         "ms_per_step": round(head["seconds"] * 1e3, 1), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "DEG construction, %s: %d x %d, %s, d=%d, k_ext=%d, eps_ext=%g, "
-                               "block limit %d; quality: %s" % (
+                               "block limit %d, lag %d; quality: %s" % (
                                    name, n, base.shape[1], "IP" if explore else "L2", d, k_ext,
-                                   eps_ext, head_b,
+                                   eps_ext, head_b, a.build_lag,
                                    "exploration recall@100 (query vertices as their own seeds)"
                                    if explore else "recall@10 of the 10,000 queries"),
                    "builds": {str(b): c for b, (_, c) in builds.items()},
@@ -818,6 +818,8 @@ def main(argv=None):
     ap.add_argument("--build", action="store_true",
                     help="time graph construction with block-batched searches (1M x 128, d=30)")
     ap.add_argument("--build-n", type=int, default=0, help="construction: first N vectors only")
+    ap.add_argument("--build-lag", type=int, default=0, choices=(0, 1),
+                    help="construction: 1 = a block searches before the previous block's edits")
     ap.add_argument("--no-quality", action="store_true",
                     help="construction: skip the search-quality sweeps of the built graphs")
     ap.add_argument("--build-batch", type=lambda s: [int(x) for x in s.split(",")],

@@ -296,7 +296,9 @@ deg_status deg_medoid(const float *vec, int64_t n, int32_t dim, int64_t stride, 
  * each on the live graph, and the changed rows are copied to `adjacency`
  * before the next block. A block holds at most `batch` vertices and at most
  * nv / 8 of the nv vertices already in the graph (at least 1); batch = 1 is
- * the one-at-a-time build.
+ * the one-at-a-time build. With lag = 1 the size limit counts only the
+ * vertices already in the graph, and the block's searches overlap the host
+ * edits of the previous block.
  *   v              the n vectors (device, DEG_F32, L2 or IP): the searched store,
  *                  whose rows are also the new vertices' queries
  *   host_vectors   the same vectors on the host (row stride host_stride floats),
@@ -312,7 +314,7 @@ deg_status deg_medoid(const float *vec, int64_t n, int32_t dim, int64_t stride, 
  *                  upload to its results on the host, microseconds of the
  *                  host edits}
  * degree even in [4, 128], n >= degree + 1, k_ext in [1, 1024], eps_ext >= 0,
- * batch >= 1. The call allocates its own device and pinned host buffers,
+ * batch >= 1, lag 0 or 1. The call allocates its own device and pinned host buffers,
  * frees them before it returns, and returns when the graph is complete on
  * `stream` (it synchronises the stream once per block). DEG_ERR_UNSUPPORTED
  * when a search result cannot supply degree neighbours (k_ext too small);
@@ -322,7 +324,9 @@ typedef struct {
     int32_t degree;  /* d */
     int32_t k_ext;   /* result size of a new vertex's search */
     float eps_ext;   /* range factor of that search */
-    int32_t reserved;
+    int32_t lag;     /* 0: a block searches the graph with every earlier block in it;
+                        1: a block searches before the previous block's edits are applied
+                        (its edits then run on the host while this block searches) */
     int64_t batch;   /* the most vertices in one block */
 } deg_build_params;
 

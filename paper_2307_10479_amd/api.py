@@ -71,7 +71,7 @@ class DegQueryDesc(C.Structure):
 
 class DegBuildParams(C.Structure):
     _fields_ = [("degree", C.c_int32), ("k_ext", C.c_int32), ("eps_ext", C.c_float),
-                ("reserved", C.c_int32), ("batch", C.c_int64)]
+                ("lag", C.c_int32), ("batch", C.c_int64)]
 
 
 EXPORTS = [
@@ -471,7 +471,7 @@ def medoid(base: torch.Tensor, metric: int = L2) -> int:
 
 
 # ------------------------------------------------------------------ construction
-def build_graph(store: VectorStore, host_base, degree, k_ext, eps_ext, batch=4096):
+def build_graph(store: VectorStore, host_base, degree, k_ext, eps_ext, batch=4096, lag=0):
     """Graph construction (Sec. 5.2, Algorithm 3 without optimizeEdge) with the
     searches of each block of new vertices batched on the GPU.
 
@@ -486,7 +486,7 @@ def build_graph(store: VectorStore, host_base, degree, k_ext, eps_ext, batch=409
     adj = torch.empty((n, degree), dtype=torch.int32, device="cuda")
     w = np.empty((n, degree), np.float32)
     cnt = np.zeros(6, np.int64)
-    p = DegBuildParams(degree=int(degree), k_ext=int(k_ext), eps_ext=float(eps_ext), reserved=0,
+    p = DegBuildParams(degree=int(degree), k_ext=int(k_ext), eps_ext=float(eps_ext), lag=int(lag),
                        batch=int(batch))
     v = store.c()
     _check("deg_build_graph", lib().deg_build_graph(

@@ -361,10 +361,12 @@ int64_t block_size(int64_t nv, int64_t batch, int64_t left) {
 struct Buffers {
     hipStream_t st;
     void *dev[6] = {};
-    void *host[4] = {};
+    void *host[8] = {};
+    hipEvent_t ev = nullptr;
     explicit Buffers(hipStream_t s) : st(s) {}
     ~Buffers() {
         (void)hipStreamSynchronize(st);
+        if (ev) (void)hipEventDestroy(ev);
         for (void *p : dev)
             if (p) (void)hipFree(p);
         for (void *p : host)
@@ -386,7 +388,7 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
         return DEG_ERR_INVALID_ARG;
     if (d < 4 || d > 128 || (d & 1) || n < (int64_t)d + 1 || n > INT32_MAX || m < 1 ||
         host_stride < m || p->k_ext < 1 || p->k_ext > 1024 || !(p->eps_ext >= 0.0f) ||
-        p->batch < 1)
+        p->batch < 1 || p->lag < 0 || p->lag > 1)
         return DEG_ERR_INVALID_ARG;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
 
@@ -410,11 +412,12 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     Buffers B(st);
     int32_t *d_seeds, *d_ids, *d_stats, *d_rows;
     float *d_ds;
-    int32_t *h_ids, *h_stats, *h_up;
-    float *h_ds;
-    // changed records per block: at most d + 1 per new vertex (the vertex and the
-    // d distinct ends of its d/2 cut edges), and the smallest DEG's before the first
-    const int64_t up_cap = cap * (d + 1) + d + 1;
+    int32_t *h_ids2[2], *h_stats2[2], *h_up;
+    float *h_ds2[2];
+    // changed records per upload: at most d + 1 per new vertex (the vertex and the
+    // d distinct ends of its d/2 cut edges) of one block, of two blocks for the last
+    // upload with lag 1, and the smallest DEG's before the first
+    const int64_t up_cap = 2 * cap * (d + 1) + d + 1;
     if (hipMalloc((void **)&d_seeds, sizeof(int32_t) * cap) != hipSuccess) return DEG_ERR_HIP;
     B.dev[0] = d_seeds;
     if (hipMalloc((void **)&d_ids, sizeof(int32_t) * cap * k) != hipSuccess) return DEG_ERR_HIP;
@@ -427,13 +430,23 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     if (hipMalloc((void **)&d_rows, rows_bytes + ws) != hipSuccess) return DEG_ERR_HIP;
     B.dev[4] = d_rows;
     void *d_ws = reinterpret_cast<char *>(d_rows) + rows_bytes;
-    if (hipHostMalloc((void **)&h_ids, sizeof(int32_t) * cap * k) != hipSuccess) return DEG_ERR_HIP;
-    B.host[0] = h_ids;
-    if (hipHostMalloc((void **)&h_ds, sizeof(float) * cap * k) != hipSuccess) return DEG_ERR_HIP;
-    B.host[1] = h_ds;
-    if (hipHostMalloc((void **)&h_stats, sizeof(int32_t) * cap * 4) != hipSuccess)
+    // two sets of host results: with lag 1 one block's results are edited in while the
+    // next block's arrive
+    for (int b = 0; b < 2; ++b) {
+        if (hipHostMalloc((void **)&h_ids2[b], sizeof(int32_t) * cap * k) != hipSuccess)
+            return DEG_ERR_HIP;
+        B.host[b == 0 ? 0 : 4] = h_ids2[b];
+        if (hipHostMalloc((void **)&h_ds2[b], sizeof(float) * cap * k) != hipSuccess)
+            return DEG_ERR_HIP;
+        B.host[b == 0 ? 1 : 5] = h_ds2[b];
+        if (hipHostMalloc((void **)&h_stats2[b], sizeof(int32_t) * cap * 4) != hipSuccess)
+            return DEG_ERR_HIP;
+        B.host[b == 0 ? 2 : 6] = h_stats2[b];
+    }
+    if (hipEventCreateWithFlags(&B.ev, hipEventDisableTiming) != hipSuccess) {
+        B.ev = nullptr;
         return DEG_ERR_HIP;
-    B.host[2] = h_stats;
+    }
     if (hipHostMalloc((void **)&h_up, sizeof(int32_t) * up_cap) != hipSuccess) return DEG_ERR_HIP;
     B.host[3] = h_up;
     int32_t *d_records = nullptr;
@@ -445,7 +458,13 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
 
     // the changed rows go to the device: their vertex ids are copied, the rows
     // themselves are read from the records by the gather kernel (the host edits
-    // them again only after the stream has been synchronised)
+    // them again only after the gather has finished: `gathering` until then)
+    bool gathering = false;
+    auto gather_done = [&]() -> bool {
+        if (!gathering) return true;
+        gathering = false;
+        return hipEventSynchronize(B.ev) == hipSuccess;
+    };
     auto upload = [&]() -> deg_status {
         const int64_t nr = (int64_t)G.dirty.size();
         if (nr == 0) return DEG_OK;
@@ -459,7 +478,10 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
         gather_rows<<<blocks, 256, 0, st>>>(adjacency, d, d_rows, nr, d_records, G.stride);
         G.dirty.clear();
         ++G.block;
-        return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
+        if (hipGetLastError() != hipSuccess || hipEventRecord(B.ev, st) != hipSuccess)
+            return DEG_ERR_HIP;
+        gathering = true;
+        return DEG_OK;
     };
 
     int64_t blocks = 0, searches = 0, phase2 = 0, lossy = 0;
@@ -467,40 +489,68 @@ extern "C" deg_status deg_build_graph(const deg_vectors *v, const float *host_ve
     clk::duration t_search{}, t_edit{};
     const float *qbase = reinterpret_cast<const float *>(v->data);
     deg_status s = DEG_OK;
-    for (int64_t s0 = (int64_t)d + 1; s0 < n;) {
-        const int64_t nv = s0;
-        const int64_t bsz = block_size(nv, cap, n - s0);
-        const clk::time_point t0 = clk::now();
-        if ((s = upload()) != DEG_OK) return s;
-        s = deg_search(v, &g, qbase + s0 * (int64_t)v->row_stride, bsz, v->row_stride, d_seeds, 1,
-                       k, p->eps_ext, &o, d_ids, d_ds, d_stats, d_ws, ws, st);
-        if (s != DEG_OK) return s;
-        if (hipMemcpyAsync(h_ids, d_ids, sizeof(int32_t) * bsz * k, hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(h_ds, d_ds, sizeof(float) * bsz * k, hipMemcpyDeviceToHost, st) !=
-                hipSuccess ||
-            hipMemcpyAsync(h_stats, d_stats, sizeof(int32_t) * bsz * 4, hipMemcpyDeviceToHost,
-                           st) != hipSuccess ||
-            hipStreamSynchronize(st) != hipSuccess)
-            return DEG_ERR_HIP;
-        const clk::time_point t1 = clk::now();
-        ++blocks;
-        searches += bsz;
+    // the edits of one block (results in set r), vertex by vertex in id order
+    auto edit_block = [&](int64_t first, int64_t count, int r) -> deg_status {
+        const int32_t *h_ids = h_ids2[r], *h_stats = h_stats2[r];
+        const float *h_ds = h_ds2[r];
         constexpr int AHEAD = 2;
-        for (int64_t i = 0; i < AHEAD && i < bsz; ++i) prefetch_result(G, h_ids + i * k, k);
-        for (int64_t i = 0; i < bsz; ++i) {
-            if (i + AHEAD < bsz) prefetch_result(G, h_ids + (i + AHEAD) * k, k);
+        for (int64_t i = 0; i < AHEAD && i < count; ++i) prefetch_result(G, h_ids + i * k, k);
+        for (int64_t i = 0; i < count; ++i) {
+            if (i + AHEAD < count) prefetch_result(G, h_ids + (i + AHEAD) * k, k);
             const int32_t fl = h_stats[i * 4 + 2];
             if (fl & DEG_FLAG_BAD_ID) return DEG_ERR_HIP;  // the device graph is corrupt
             if (fl & DEG_FLAG_QUEUE_OVERFLOW) ++lossy;
             int ns = 0;
             while (ns < k && h_ids[i * k + ns] >= 0) ++ns;
-            if (!extend_vertex(G, host_vectors, host_stride, m, v->metric, (int32_t)(s0 + i),
+            if (!extend_vertex(G, host_vectors, host_stride, m, v->metric, (int32_t)(first + i),
                                h_ids + i * k, h_ds + i * k, ns, phase2))
                 return DEG_ERR_UNSUPPORTED;  // the search result cannot supply d neighbours
         }
-        t_search += t1 - t0;
-        t_edit += clk::now() - t1;
+        return DEG_OK;
+    };
+    const bool lag = p->lag == 1;
+    int cur = 0;
+    int64_t pend_s = 0, pend_n = 0;  // lag 1: the block whose edits come after the next searches
+    for (int64_t s0 = (int64_t)d + 1; s0 < n || pend_n > 0;) {
+        // vertices already in the graph: all but the pending block
+        const int64_t bsz = s0 < n ? block_size(s0 - pend_n, cap, n - s0) : 0;
+        clk::time_point t0 = clk::now();
+        if (bsz > 0) {
+            if ((s = upload()) != DEG_OK) return s;
+            s = deg_search(v, &g, qbase + s0 * (int64_t)v->row_stride, bsz, v->row_stride, d_seeds,
+                           1, k, p->eps_ext, &o, d_ids, d_ds, d_stats, d_ws, ws, st);
+            if (s != DEG_OK) return s;
+            if (hipMemcpyAsync(h_ids2[cur], d_ids, sizeof(int32_t) * bsz * k,
+                               hipMemcpyDeviceToHost, st) != hipSuccess ||
+                hipMemcpyAsync(h_ds2[cur], d_ds, sizeof(float) * bsz * k, hipMemcpyDeviceToHost,
+                               st) != hipSuccess ||
+                hipMemcpyAsync(h_stats2[cur], d_stats, sizeof(int32_t) * bsz * 4,
+                               hipMemcpyDeviceToHost, st) != hipSuccess)
+                return DEG_ERR_HIP;
+            ++blocks;
+            searches += bsz;
+        }
+        if (lag && pend_n > 0) {
+            // the previous block's edits run while this block searches
+            if (!gather_done()) return DEG_ERR_HIP;
+            t_search += clk::now() - t0;
+            t0 = clk::now();
+            if ((s = edit_block(pend_s, pend_n, cur ^ 1)) != DEG_OK) return s;
+            t_edit += clk::now() - t0;
+            t0 = clk::now();
+        }
+        if (bsz > 0 && hipStreamSynchronize(st) != hipSuccess) return DEG_ERR_HIP;
+        gathering = false;
+        t_search += clk::now() - t0;
+        if (lag) {
+            pend_s = s0;
+            pend_n = bsz;
+            cur ^= 1;
+        } else if (bsz > 0) {
+            t0 = clk::now();
+            if ((s = edit_block(s0, bsz, cur)) != DEG_OK) return s;
+            t_edit += clk::now() - t0;
+        }
         s0 += bsz;
     }
     if ((s = upload()) != DEG_OK) return s;

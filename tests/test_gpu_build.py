@@ -26,9 +26,9 @@ def A():
     return api
 
 
-def gpu_build(A, x, d, k_ext, eps, batch, metric=oracle.L2):
+def gpu_build(A, x, d, k_ext, eps, batch, metric=oracle.L2, lag=0):
     store = A.VectorStore(torch.from_numpy(np.ascontiguousarray(x)).cuda(), "f32", metric)
-    adj, w, cnt = A.build_graph(store, x, d, k_ext, eps, batch)
+    adj, w, cnt = A.build_graph(store, x, d, k_ext, eps, batch, lag=lag)
     torch.cuda.synchronize()
     return adj.cpu().numpy(), w, cnt
 
@@ -63,6 +63,26 @@ def test_build_matches_oracle_schedule(A, n, m, d, batch, metric):
     if batch == 1:
         sa, sw, _ = oracle.build_graph(x, d, metric, k_ext=k_ext, eps_ext=eps, do_opt=False)
         assert (adj == sa).all() and (w == sw).all()
+
+
+@pytest.mark.parametrize("n,m,d,batch,metric", [
+    (1500, 24, 10, 16, oracle.L2),
+    (1200, 20, 12, 64, oracle.IP),
+    (2500, 33, 30, 4096, oracle.L2),
+])
+def test_build_with_lag_matches_oracle_schedule(A, n, m, d, batch, metric):
+    # a block searches before the previous block's edits (which the host applies
+    # meanwhile): the oracle's lag-1 schedule, byte for byte
+    x = synth.small_int(60 + d, n, m, hi=64) if metric == oracle.L2 else synth.small_unit(61, n, m)
+    say("build lag 1", n, m, d, batch, metric)
+    adj, w, cnt = gpu_build(A, x, d, 2 * d, 0.2, batch, metric, lag=1)
+    assert cnt["lossy"] == 0 and cnt["searches"] == n - d - 1
+    ra, rw, rc = oracle.build_graph_batched(x, d, batch, metric, k_ext=2 * d, eps_ext=0.2,
+                                            do_opt=False, lag=1)
+    assert (adj == ra).all(), "adjacency differs in %d rows" % int((adj != ra).any(1).sum())
+    assert (w == rw).all()
+    assert cnt["phase2"] == rc["phase2"]
+    check(adj, w, x, metric)
 
 
 def test_build_cfg2_subset(A):

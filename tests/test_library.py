@@ -89,15 +89,16 @@ def test_build_argument_validation(L):
     from paper_2307_10479_amd import api
     P = C.c_void_p(0x400000)
 
-    def call(degree=10, k_ext=20, eps=0.2, batch=64, dtype=0, n=100, dim=16, stride=16, hstride=16):
+    def call(degree=10, k_ext=20, eps=0.2, batch=64, dtype=0, n=100, dim=16, stride=16, hstride=16,
+             lag=0):
         v = api.DegVectors()
         v.data, v.n, v.dim, v.row_stride, v.dtype, v.metric = P, n, dim, stride, dtype, 0
-        p = api.DegBuildParams(degree=degree, k_ext=k_ext, eps_ext=eps, reserved=0, batch=batch)
+        p = api.DegBuildParams(degree=degree, k_ext=k_ext, eps_ext=eps, lag=lag, batch=batch)
         return L.deg_build_graph(C.byref(v), P, hstride, C.byref(p), P, None, None, None)
 
     bad = [call(degree=5), call(degree=2), call(degree=130), call(k_ext=0), call(k_ext=2000),
            call(eps=-1.0), call(eps=float("nan")), call(batch=0), call(dtype=1), call(n=10),
-           call(hstride=8)]
+           call(hstride=8), call(lag=2), call(lag=-1)]
     assert all(b == 1 for b in bad), bad
 
 
