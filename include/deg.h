@@ -335,9 +335,10 @@ deg_status deg_build_graph(const deg_vectors *v, const float *host_vectors, int6
                            int64_t *counters, void *stream);
 
 /*
- * MRNG conformity of every edge (Algorithm 2): the selection step of the
- * dynamic edge optimisation (Algorithm 5 optimises a vertex's edges that fail
- * it). Edge (v1, v2) fails when a common neighbour u of v1 and v2 has
+ * MRNG conformity of every edge (Algorithm 2) and every vertex's longest edge:
+ * the selection step of the dynamic edge optimisation (Algorithm 5 optimises a
+ * vertex's edges that fail the check, then its longest edge). Edge (v1, v2)
+ * fails when a common neighbour u of v1 and v2 has
  * max(w(v1, u), w(v2, u)) < w(v1, v2); only stored weights are compared.
  *   g          device adjacency (degree <= 128; id -1 marks an empty slot)
  *   weights    device, n rows of w_stride FP32: weights[v][j] is the weight of
@@ -346,10 +347,13 @@ deg_status deg_build_graph(const deg_vectors *v, const float *host_vectors, int6
  *              slot is empty (or holds an id outside [0, n))
  *   out_fail_count nullable device int64: the number of failing entries (each
  *              undirected edge is counted from both ends)
+ *   out_longest nullable device int32[n]: the slot of the vertex's longest edge
+ *              (equal weights: the smaller neighbour id; -1 for an empty row)
  * Asynchronous on `stream`; allocates nothing.
  */
 deg_status deg_graph_check_mrng(const deg_graph *g, const float *weights, int64_t w_stride,
-                                uint8_t *out_ok, int64_t *out_fail_count, void *stream);
+                                uint8_t *out_ok, int64_t *out_fail_count, int32_t *out_longest,
+                                void *stream);
 
 /* Reduced-precision stores. BF16: round to nearest even. FP8: per row
  * scale = max|x| / 448 (1 if the row is zero), code = E4M3 round to nearest

@@ -103,7 +103,7 @@ def load_library(path: Path | None = None):
         "deg_search_workspace_bytes": (SZ, [pv, pg, I64, I32, po]),
         "deg_search_resident_waves": (I32, [pv, pg, I32, po]),
         "deg_build_graph": (I32, [pv, P, I64, C.POINTER(DegBuildParams), P, P, P, V]),
-        "deg_graph_check_mrng": (I32, [pg, P, I64, P, P, V]),
+        "deg_graph_check_mrng": (I32, [pg, P, I64, P, P, P, V]),
         "deg_search": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, P, SZ, V]),
         "deg_search_noalloc": (I32, [pv, pg, P, I64, I64, P, I32, I32, F, po, P, P, P, V]),
         "deg_search_indexed": (I32, [pv, pg, P, I64, I32, F, po, P, P, P, P, SZ, V]),
@@ -497,19 +497,22 @@ def build_graph(store: VectorStore, host_base, degree, k_ext, eps_ext, batch=409
 
 
 def check_mrng(graph: DeviceGraph, weights: torch.Tensor):
-    """MRNG conformity of every edge (Algorithm 2). weights: (n, >= degree) FP32 on
-    the device, row-aligned with the adjacency. Returns (ok (n, degree) uint8 on the
-    device: 1 passes, 0 fails, 255 empty slot; number of failing entries)."""
+    """MRNG conformity of every edge (Algorithm 2) and every vertex's longest edge.
+    weights: (n, >= degree) FP32 on the device, row-aligned with the adjacency.
+    Returns (ok (n, degree) uint8 on the device: 1 passes, 0 fails, 255 empty slot;
+    number of failing entries; slot of each vertex's longest edge (n,) int32)."""
     n, d = graph.n, graph.degree
     if not (weights.is_cuda and weights.dtype == torch.float32 and weights.dim() == 2
             and weights.shape[0] == n and weights.shape[1] >= d and weights.stride(1) == 1):
         raise ValueError("weights must be a (n, >= degree) float32 device tensor")
     ok = torch.empty((n, d), dtype=torch.uint8, device="cuda")
     cnt = torch.zeros(1, dtype=torch.int64, device="cuda")
+    longest = torch.empty(n, dtype=torch.int32, device="cuda")
     g = graph.c()
     _check("deg_graph_check_mrng", lib().deg_graph_check_mrng(
-        C.byref(g), _ptr(weights), weights.stride(0), _ptr(ok), _ptr(cnt), _stream()))
-    return ok, cnt
+        C.byref(g), _ptr(weights), weights.stride(0), _ptr(ok), _ptr(cnt), _ptr(longest),
+        _stream()))
+    return ok, cnt, longest
 
 
 # ------------------------------------------------------------------ MLP

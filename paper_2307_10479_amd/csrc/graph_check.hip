@@ -1,6 +1,7 @@
-// MRNG conformity of every edge (Algorithm 2), the selection step of the
-// dynamic edge optimisation (Algorithm 5 optimises the edges of a vertex that
-// fail it, and its longest edge), evaluated for the whole graph at once.
+// MRNG conformity of every edge (Algorithm 2) and the longest edge of every
+// vertex: the selection step of the dynamic edge optimisation (Algorithm 5
+// optimises the edges of a vertex that fail the check, then its longest edge),
+// evaluated for the whole graph at once.
 //
 // An edge (v1, v2) fails when a common neighbour u of v1 and v2 has both of
 // its edges to them shorter than the edge itself: delta(v1, v2) >
@@ -24,7 +25,8 @@ constexpr int MAXD = 128;
 
 __global__ void __launch_bounds__(WAVE) mrng_kernel(const int32_t *adj, int64_t astride,
                                                     const float *w, int64_t wstride, int64_t n,
-                                                    int d, uint8_t *ok, unsigned long long *fails) {
+                                                    int d, uint8_t *ok, unsigned long long *fails,
+                                                    int32_t *longest) {
     __shared__ int32_t rid[MAXD];
     __shared__ float rw[MAXD];
     const int lane = (int)threadIdx.x;
@@ -57,6 +59,16 @@ __global__ void __launch_bounds__(WAVE) mrng_kernel(const int32_t *adj, int64_t 
             }
             ok[v1 * (int64_t)d + j] = res;
         }
+        if (longest != nullptr && lane == 0) {
+            // the slot of v1's longest edge (equal weights: the smaller neighbour id)
+            int best = -1;
+            for (int j = 0; j < d; ++j) {
+                const int32_t u = rid[j];
+                if (u < 0 || u >= n) continue;
+                if (best < 0 || rw[j] > rw[best] || (rw[j] == rw[best] && u < rid[best])) best = j;
+            }
+            longest[v1] = best;
+        }
         __syncthreads();
     }
     // one atomic per lane that saw a failing edge
@@ -69,7 +81,8 @@ __global__ void zero_u64(unsigned long long *p) { *p = 0; }
 
 extern "C" deg_status deg_graph_check_mrng(const deg_graph *g, const float *weights,
                                            int64_t w_stride, uint8_t *out_ok,
-                                           int64_t *out_fail_count, void *stream) {
+                                           int64_t *out_fail_count, int32_t *out_longest,
+                                           void *stream) {
     if (!g || !g->adj || !weights || !out_ok || g->n < 1 || g->degree < 1 ||
         g->degree > MAXD || g->row_stride < g->degree || w_stride < g->degree)
         return DEG_ERR_INVALID_ARG;
@@ -78,6 +91,7 @@ extern "C" deg_status deg_graph_check_mrng(const deg_graph *g, const float *weig
     if (fails) hipLaunchKernelGGL(zero_u64, dim3(1), dim3(1), 0, st, fails);
     const int64_t blocks = g->n < 65536 ? g->n : 65536;
     hipLaunchKernelGGL(mrng_kernel, dim3((unsigned)blocks), dim3(WAVE), 0, st, g->adj,
-                       (int64_t)g->row_stride, weights, w_stride, g->n, g->degree, out_ok, fails);
+                       (int64_t)g->row_stride, weights, w_stride, g->n, g->degree, out_ok, fails,
+                       out_longest);
     return hipGetLastError() == hipSuccess ? DEG_OK : DEG_ERR_HIP;
 }

@@ -39,11 +39,23 @@ def oracle_flags(x, adj, w, metric, vertices):
     return out
 
 
-def gpu_flags(A, adj, w):
+def gpu_flags(A, adj, w, with_longest=False):
     G = A.DeviceGraph(torch.from_numpy(np.ascontiguousarray(adj)).cuda())
-    ok, cnt = A.check_mrng(G, torch.from_numpy(np.ascontiguousarray(w)).cuda())
+    ok, cnt, longest = A.check_mrng(G, torch.from_numpy(np.ascontiguousarray(w)).cuda())
     torch.cuda.synchronize()
+    if with_longest:
+        return ok.cpu().numpy(), int(cnt.item()), longest.cpu().numpy()
     return ok.cpu().numpy(), int(cnt.item())
+
+
+def longest_by_definition(adj, w):
+    # the largest weight of the row; equal weights: the smaller neighbour id
+    out = np.full(len(adj), -1, np.int32)
+    for v in range(len(adj)):
+        live = [j for j in range(adj.shape[1]) if adj[v, j] >= 0]
+        if live:
+            out[v] = max(live, key=lambda j: (float(w[v, j]), -int(adj[v, j])))
+    return out
 
 
 @pytest.mark.parametrize("n,m,d,metric,do_opt", [
@@ -56,9 +68,10 @@ def test_mrng_flags_match_oracle(A, n, m, d, metric, do_opt):
     x = synth.small_int(50 + d, n, m, hi=64) if metric == oracle.L2 else synth.small_unit(51, n, m)
     adj, w, _ = oracle.build_graph(x, d, metric, k_ext=2 * d, eps_ext=0.2, k_opt=d, do_opt=do_opt)
     say("mrng", n, m, d, metric, do_opt)
-    ok, nfail = gpu_flags(A, adj, w)
+    ok, nfail, longest = gpu_flags(A, adj, w, with_longest=True)
     ref = oracle_flags(x, adj, w, metric, np.arange(n))
     assert (ok == ref).all(), "%d entries differ" % int((ok != ref).sum())
+    assert (longest == longest_by_definition(adj, w)).all()
     assert nfail == int((ref == 0).sum())
     assert 0 < nfail < n * d  # both outcomes occur
 
@@ -68,7 +81,8 @@ def test_mrng_empty_slots_and_planted_failure(A):
     # empty slots report 255
     adj = np.array([[1, 2, -1, -1], [0, 2, -1, -1], [0, 1, -1, -1]], np.int32)
     w = np.array([[5, 1, 0, 0], [5, 2, 0, 0], [1, 2, 0, 0]], np.float32)
-    ok, nfail = gpu_flags(A, adj, w)
+    ok, nfail, longest = gpu_flags(A, adj, w, with_longest=True)
+    assert longest.tolist() == [0, 0, 1]
     assert ok[:, 2:].tolist() == [[255, 255]] * 3
     assert ok[0, 0] == 0 and ok[1, 0] == 0  # (0, 1) from both ends
     assert ok[0, 1] == 1 and ok[2, 0] == 1 and ok[1, 1] == 1 and ok[2, 1] == 1

@@ -106,11 +106,11 @@ def test_mrng_check_argument_validation(L):
     from paper_2307_10479_amd import api
     P = C.c_void_p(0x400000)
     g = api.DegGraph(0x400000, 100, 10, 10)
-    assert L.deg_graph_check_mrng(None, P, 10, P, None, None) == 1
-    assert L.deg_graph_check_mrng(C.byref(g), None, 10, P, None, None) == 1
-    assert L.deg_graph_check_mrng(C.byref(g), P, 8, P, None, None) == 1   # weight rows too short
+    assert L.deg_graph_check_mrng(None, P, 10, P, None, None, None) == 1
+    assert L.deg_graph_check_mrng(C.byref(g), None, 10, P, None, None, None) == 1
+    assert L.deg_graph_check_mrng(C.byref(g), P, 8, P, None, None, None) == 1  # rows too short
     g = api.DegGraph(0x400000, 100, 130, 130)
-    assert L.deg_graph_check_mrng(C.byref(g), P, 130, P, None, None) == 1  # degree above 128
+    assert L.deg_graph_check_mrng(C.byref(g), P, 130, P, None, None, None) == 1  # degree > 128
 
 
 def test_knn_and_mlp_argument_validation(L):
