@@ -344,9 +344,11 @@ def test_parity_cfg2_full_size_sampled(A):
     seeds = dev(np.full((q.shape[0], 1), seed, np.int32))
     sample = synth.rng(70).choice(q.shape[0], size=300, replace=False)
     # the last settings are the benchmark's operating points (eps 0.19 with the
-    # capacities it sweeps, 256 LDS visited slots)
+    # capacities it sweeps and the LDS visited slots it tunes: the exact, overflow-free
+    # L = 16384 with 512 and 1,024 slots)
     for eps, L, hs in ((0.0, 256, 0), (0.1, 256, 0), (0.15, 1024, 0), (0.19, 1024, 256),
-                       (0.19, 2048, 256), (0.19, 4096, 256)):
+                       (0.19, 2048, 256), (0.19, 4096, 256), (0.19, 16384, 512),
+                       (0.19, 16384, 1024)):
         say("cfg2 eps", eps, "L", L, "hash slots", hs)
         ids, ds, st = A.search(store32, G, dev(q), seeds, 10, eps, queue_cap=L, hash_slots=hs)
         ids16, ds16, st16 = A.search(store16, G, dev(q), seeds, 10, eps, queue_cap=L,
