@@ -314,7 +314,8 @@ deg_status deg_medoid(const float *vec, int64_t n, int32_t dim, int64_t stride, 
  *                  upload to its results on the host, microseconds of the
  *                  host edits}
  * degree even in [4, 128], n >= degree + 1, k_ext in [1, 1024], eps_ext >= 0,
- * batch >= 1, lag 0 or 1. The call allocates its own device and pinned host buffers,
+ * batch >= 1, lag 0 or 1. The call allocates its own device and pinned host buffers
+ * (the host graph takes n x round_up(2 + 2 degree, 16) x 4 bytes of pinned memory),
  * frees them before it returns, and returns when the graph is complete on
  * `stream` (it synchronises the stream once per block). DEG_ERR_UNSUPPORTED
  * when a search result cannot supply degree neighbours (k_ext too small);
