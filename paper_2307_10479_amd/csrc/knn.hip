@@ -503,6 +503,7 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P, int p2) {
     extern __shared__ __align__(16) unsigned char smem[];
     uint64_t *keys = reinterpret_cast<uint64_t *>(smem);       // nslices * kc
     uint64_t *top = keys + (size_t)P.nslices * P.kc;            // p2 (power of two >= k)
+    int32_t *hist = reinterpret_cast<int32_t *>(top + p2);     // 256 bins
     const int lane = lane_id(), p = lane & 31;
     const int64_t qi = blockIdx.x;
     if (qi >= P.nq) return;
@@ -535,20 +536,46 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P, int p2) {
         }
     }
     wave_sync();
-    // the k smallest keys (the k-th built bit by bit), then sorted
+    // the k smallest keys, then sorted: the k-th smallest key (keys are distinct) is
+    // found one byte at a time, most significant first, from a 256-bin histogram of
+    // the keys that share the bytes fixed so far
     const int kk = min(P.k, tot);
     uint64_t kth = KEY_MAX;
     if (tot > kk) {
-        uint64_t ans = 0;
-        for (int b = 63; b >= 0; --b) {
-            uint64_t cand = ans | (1ull << b);
-            int c = 0;
-            for (int i = lane; i < tot; i += WAVE) c += keys[i] < cand ? 1 : 0;
+        uint64_t prefix = 0;
+        int need = kk;  // rank of the wanted key among those sharing `prefix`
+        for (int pass = 0; pass < 8; ++pass) {
+            const int shift = 56 - 8 * pass;
+            const uint64_t hmask = pass == 0 ? 0ull : (~0ull << (shift + 8));
+            for (int i = lane; i < 256; i += WAVE) hist[i] = 0;
+            wave_sync();
+            for (int i = lane; i < tot; i += WAVE) {
+                const uint64_t v = keys[i];
+                if ((v & hmask) == prefix) atomicAdd(&hist[(int)((v >> shift) & 255u)], 1);
+            }
+            wave_sync();
+            // lane l holds bins 4l .. 4l + 3; an inclusive scan over the lanes
+            const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1];
+            const int h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+            const int own = h0 + h1 + h2 + h3;
+            int inc = own;
 #pragma unroll
-            for (int m = 32; m >= 1; m >>= 1) c += __shfl_xor(c, m);
-            if (c < kk) ans = cand;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const int t = __shfl_up(inc, o);
+                if (lane >= o) inc += t;
+            }
+            const int exc = inc - own;
+            const uint64_t hit = ballot(exc < need && need <= inc);
+            const int hl = (int)__builtin_ctzll(hit);
+            int r = need - exc, dg = 4 * lane;
+            if (r > h0) { r -= h0; dg += 1;
+                if (r > h1) { r -= h1; dg += 1;
+                    if (r > h2) { r -= h2; dg += 1; } } }
+            need = __shfl(r, hl);
+            prefix |= (uint64_t)__shfl(dg, hl) << shift;
+            wave_sync();
         }
-        kth = ans;
+        kth = prefix;
     }
     int out = 0;
     for (int base = 0; base < tot; base += WAVE) {
@@ -681,7 +708,7 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
     int q = ((dim + 3) / 4 + 31) / 32;
     int qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
     const int p2 = pow2_ge(k);
-    size_t lds = (size_t)P.nslices * P.kc * 8 + (size_t)p2 * 8;
+    size_t lds = (size_t)P.nslices * P.kc * 8 + (size_t)p2 * 8 + 256 * 4;
     void (*fn)(KnnParams, int) = nullptr;
     if (metric == DEG_METRIC_L2)
         fn = qch == 1 ? knn_final_kernel<DEG_METRIC_L2, 1>
