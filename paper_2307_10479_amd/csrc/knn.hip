@@ -501,8 +501,7 @@ __device__ void bitonic_sort(uint64_t *a, int n8) {
 template <int METRIC, int QCH>
 __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P, int p2) {
     extern __shared__ __align__(16) unsigned char smem[];
-    uint64_t *keys = reinterpret_cast<uint64_t *>(smem);       // nslices * kc
-    uint64_t *top = keys + (size_t)P.nslices * P.kc;            // p2 (power of two >= k)
+    uint64_t *top = reinterpret_cast<uint64_t *>(smem);        // p2 (power of two >= k)
     int32_t *hist = reinterpret_cast<int32_t *>(top + p2);     // 256 bins
     const int lane = lane_id(), p = lane & 31;
     const int64_t qi = blockIdx.x;
@@ -521,7 +520,10 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P, int p2) {
         qv[c] = make_float4(b + 0 < P.dim ? qp[b + 0] : 0.f, b + 1 < P.dim ? qp[b + 1] : 0.f,
                             b + 2 < P.dim ? qp[b + 2] : 0.f, b + 3 < P.dim ? qp[b + 3] : 0.f);
     }
-    // exact FP32 distances of every candidate
+    // exact FP32 distances of every candidate, written back compacted at the start of
+    // the query's own list region (slice s is read at s * cap, and the keys written
+    // so far end at or before s * kc < s * cap: a write never overtakes a read)
+    uint64_t *keys = P.lists + qi * P.nslices * P.cap;
     int tot = 0;
     for (int s = 0; s < P.nslices; ++s) {
         const uint64_t *lst = P.lists + (qi * P.nslices + s) * P.cap;
@@ -535,6 +537,7 @@ __global__ void __launch_bounds__(64) knn_final_kernel(KnnParams P, int p2) {
             tot += nc;
         }
     }
+    __threadfence_block();
     wave_sync();
     // the k smallest keys, then sorted: the k-th smallest key (keys are distinct) is
     // found one byte at a time, most significant first, from a 256-bin histogram of
@@ -708,7 +711,7 @@ extern "C" deg_status deg_knn_bruteforce(const float *base, int64_t n, int32_t d
     int q = ((dim + 3) / 4 + 31) / 32;
     int qch = q <= 1 ? 1 : (q <= 2 ? 2 : (q <= 4 ? 4 : 12));
     const int p2 = pow2_ge(k);
-    size_t lds = (size_t)P.nslices * P.kc * 8 + (size_t)p2 * 8 + 256 * 4;
+    size_t lds = (size_t)p2 * 8 + 256 * 4;
     void (*fn)(KnnParams, int) = nullptr;
     if (metric == DEG_METRIC_L2)
         fn = qch == 1 ? knn_final_kernel<DEG_METRIC_L2, 1>
