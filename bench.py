@@ -898,7 +898,8 @@ def main(argv=None):
 
     def run(method, eps, model=None, out=None, L=0, QQ=None, SS=None, kk=None):
         store = s32 if method == "P" else s16
-        tn = tuned.get("P" if method == "P" else "B", {})
+        tn = tuned.get("P" if method == "P" else
+                       ("BL" if method.startswith("BL") and "BL" in tuned else "B"), {})
         return api.search(store, G, Q if QQ is None else QQ, seeds if SS is None else SS,
                           k if kk is None else kk, eps, out=out, queue_cap=L,
                           stop=model if method.startswith("BL") else None, **tn)
@@ -1070,6 +1071,12 @@ def main(argv=None):
         params, mean, inv_std = models[a.stop_interval]
         model = stop.build_model(params, mean, inv_std, tau, a.stop_interval, opBL["tau_long"],
                                  opBL["long_hops"])
+        # the stop variant has its own register and LDS budget: its launch is tuned at
+        # its operating point too (the knobs do not change results)
+        best, _table = tune.tune(s16, G, V, vseeds, k, opBL["eps"], save=False,
+                                 queue_cap=opBL["L"], stop=model)
+        tuned["BL"] = dict(hash_slots=best["hash_slots"], waves_per_cu=best["waves_per_cu"])
+        log("stop variant tuned at its operating point: %s" % tuned["BL"])
         if a.save_state:
             info = dict(tuned=tuned, ops=dict(P=opP, B=opB, BL=opBL), tau=tau,
                         interval=a.stop_interval)
