@@ -14,8 +14,10 @@
 // the rows they changed go back to the device before the next block. A block
 // holds at most `batch` vertices and at most an eighth of the graph (at least
 // one), so the first blocks are single vertices and batch = 1 is the paper's
-// schedule. The optional optimizeEdge step (Algorithm 4) is not part of this
-// entry point: its searches depend on each other's edits.
+// schedule. With lag 1 a block searches before the previous block's edits are
+// applied, so that the host applies them while the device searches. The
+// optional optimizeEdge step (Algorithm 4) is not part of this entry point: its
+// searches depend on each other's edits.
 #include <hip/hip_runtime.h>
 #include <immintrin.h>
 
